@@ -1,0 +1,93 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke
+check.
+
+This module only draws inputs: workload parameters, nodal source values and
+random vectors.  It holds none of the solver's arithmetic (no assembly, no
+operator, no load-vector integration), so the CPU oracle and the GPU library
+receive identical inputs without sharing any code path.
+
+Workloads (names describe the problem; all use delta = 0, delta_hat = k,
+Sommerfeld conditions on every face and V(2,2) scaled Jacobi, omega = 2/3):
+
+  p1-64-k10        2D P1, 64 x 64 right-diagonal mesh, k = 10, 3 levels,
+                   one Gaussian at (0.5, 0.5), sigma 0.05, complex FP64
+  p1-1024-k100     2D P1, 1024 x 1024, k = 100, 8 levels, four Gaussians at
+                   seeded uniform centres (PCG64 seed 0), sigma 0.02, FP64
+  p1-2048-k200     2D P1, 2048 x 2048, k = 200, 8 levels (coarsest 16 x 16),
+                   Gaussian at (0.5, 0.5), sigma 0.05, FP32 multigrid with
+                   FP64 outer iteration
+  q1-256-k40       3D Q1, 256^3 hexahedra, k = 40, 6 levels, one Gaussian at a
+                   seeded uniform centre (seed 0), sigma 0.03, FP32 multigrid
+The paper's own sources (uniform f = 1 and the box source on
+[0.4, 0.6]^2) are available for the paper-setting checks.
+"""
+
+import numpy as np
+
+WORKLOADS = {
+    "p1-64-k10": dict(dim=2, n=64, k=10.0, delta=0.0, delta_hat=10.0, levels=3,
+                      nrhs=1, precision="fp64", sigma=0.05, centres="centre"),
+    "p1-1024-k100": dict(dim=2, n=1024, k=100.0, delta=0.0, delta_hat=100.0, levels=8,
+                         nrhs=4, precision="fp64", sigma=0.02, centres="seed0"),
+    "p1-2048-k200": dict(dim=2, n=2048, k=200.0, delta=0.0, delta_hat=200.0, levels=8,
+                         nrhs=1, precision="fp32mg", sigma=0.05, centres="centre"),
+    "q1-256-k40": dict(dim=3, n=256, k=40.0, delta=0.0, delta_hat=40.0, levels=6,
+                       nrhs=1, precision="fp32mg", sigma=0.03, centres="seed0"),
+}
+
+
+def seeded_centres(count, dim, seed):
+    """Source centres uniform on (0, 1)^dim from numpy's PCG64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(0.0, 1.0, size=(count, dim))
+
+
+def workload_centres(name):
+    w = WORKLOADS[name]
+    if w["centres"] == "centre":
+        return np.full((w["nrhs"], w["dim"]), 0.5)
+    return seeded_centres(w["nrhs"], w["dim"], 0)
+
+
+def node_coordinates(dim, n):
+    """Nodal coordinates, lexicographic with x fastest, spacing 1/n."""
+    t = np.arange(n + 1, dtype=np.float64) / n
+    if dim == 2:
+        y, x = np.meshgrid(t, t, indexing="ij")
+        return [x.ravel(), y.ravel()]
+    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+    return [x.ravel(), y.ravel(), z.ravel()]
+
+
+def gaussian_nodal(dim, n, centre, sigma):
+    """Nodal values of exp(-|x - centre|^2 / (2 sigma^2)), amplitude 1."""
+    xs = node_coordinates(dim, n)
+    r2 = sum((x - c) ** 2 for x, c in zip(xs, centre))
+    return np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def workload_sources(name, n=None):
+    """Nodal Gaussian sources (nrhs, N) of a named workload (optionally on a
+    different mesh size n, for reduced parity cases)."""
+    w = WORKLOADS[name]
+    nn = w["n"] if n is None else n
+    return np.stack([gaussian_nodal(w["dim"], nn, c, w["sigma"])
+                     for c in workload_centres(name)])
+
+
+def uniform_source(dim, n):
+    """The paper's uniform source f = 1 (nodal values)."""
+    return np.ones((n + 1) ** dim)
+
+
+def box_source(n):
+    """The paper's box source: 1 on [0.4, 0.6]^2, 0 elsewhere (nodal)."""
+    x, y = node_coordinates(2, n)
+    inside = (x >= 0.4 - 1e-12) & (x <= 0.6 + 1e-12) & (y >= 0.4 - 1e-12) & (y <= 0.6 + 1e-12)
+    return inside.astype(np.float64)
+
+
+def random_complex(shape, seed):
+    """Standard complex normal array (real and imaginary parts N(0, 1))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
