@@ -1,0 +1,233 @@
+/*
+ * helm.h -- C ABI of the MI355X shifted-HSS Helmholtz solver.
+ *
+ * Problem (Sec. 2 of Cotter, Hope-Collins and Knook, "Shifted HSS solvers
+ * for the indefinite Helmholtz equation"):  find u in the CG1/Q1 space with
+ *
+ *     b_delta(u, v) = G[v]  for all v,
+ *     b_delta(u, v) = int (-delta + ik)^2 u v* + grad u . grad v*
+ *                     - (-delta + ik) int_Gamma u v*,
+ *
+ * on the unit square (P1 triangles, every cell split along the diagonal
+ * from (x_i, y_j) to (x_i+1, y_j+1)) or the unit cube (Q1 hexahedra), with
+ * Sommerfeld conditions on Gamma = the whole boundary.  delta >= 0, k > 0.
+ *
+ * Method: right-preconditioned flexible GMRES in complex FP64 on B_0 (or
+ * B_delta), preconditioned by the shifted-HSS preconditioner of Sec. 4
+ * (Definition "Shifted HSS iteration for the primal system",
+ * eq. (HSSpc primal)) with delta replaced by delta_hat > delta:
+ * m*ceil(k) gamma=k HSS steps from u_0 = 0, each inner solve with
+ *     L = K + (dh^2 - k^2 - 2i dh k^2) M + (dh - i k^2) M_Gamma
+ * approximated by one geometric-multigrid V(nu1,nu2) cycle with scaled
+ * Jacobi smoothing (Sec. 5.3), FE interpolation / its transpose as
+ * transfers, and an FP64 dense solve on the coarsest mesh.
+ *
+ * Data layout (all vectors): complex, interleaved (re, im), one column per
+ * right-hand side, column-major [nrhs][N]; nodes lexicographic,
+ * node (i, j[, l]) at index i + (n+1) (j + (n+1) l), N = (n+1)^dim.
+ * FP64 vectors are double2, FP32 vectors float2.  Every vector pointer
+ * passed to this library is a DEVICE pointer on the device current when
+ * helm_create was called; the caller owns it and it is not retained after
+ * the call returns.
+ *
+ * Streams: all device work is ordered on the stream given to helm_create.
+ * Calls that report host-visible results (helm_solve) synchronise that
+ * stream before returning; the per-step calls only enqueue work.
+ * A handle is not thread-safe; distinct handles are independent.
+ *
+ * Errors: every call returns HELM_OK (0) or a negative HELM_E* code; no
+ * exception crosses the ABI; helm_strerror names the code.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HELM_OK        0
+#define HELM_EINVAL   (-1)  /* invalid argument (sizes, parameters, null)  */
+#define HELM_ENOMEM   (-2)  /* host or device allocation failed            */
+#define HELM_EDEVICE  (-3)  /* HIP runtime error                           */
+#define HELM_ENOCONV  (-4)  /* max_outer reached before the tolerance      */
+#define HELM_ENOTSUP  (-5)  /* valid request this build does not implement */
+
+/* ---- mesh / element kinds ---------------------------------------------- */
+#define HELM_P1_TRI_RIGHT 1  /* 2D, right-diagonal P1 triangles */
+#define HELM_Q1_HEX       2  /* 3D, trilinear hexahedra          */
+
+/* ---- precision modes ---------------------------------------------------- */
+#define HELM_FP64     0  /* everything in complex FP64                       */
+#define HELM_FP32_MG  1  /* HSS sweeps and V-cycles in complex FP32 (FP32
+                            accumulation); outer FGMRES, Arnoldi and the
+                            coarsest-mesh solve stay FP64                    */
+
+/* ---- operators for helm_apply (all a K + b M + c M_Gamma) --------------- */
+#define HELM_OP_B0      0  /* b_0: K - k^2 M - i k M_Gamma (Sec. 2, delta = 0) */
+#define HELM_OP_BDELTA  1  /* b_delta with the handle's delta                 */
+#define HELM_OP_BSHIFT  2  /* b_delta_hat                                    */
+#define HELM_OP_L       3  /* L of eq. (HSSpc primal), left-hand side        */
+#define HELM_OP_N       4  /* N of eq. (HSSpc primal), right-hand operator   */
+#define HELM_OP_H       5  /* Gram matrix of the H_primal inner product
+                              (Sec. 3.1) with delta_hat: 2 dh k M + k M_Gamma */
+#define HELM_OP_M       6  /* mass matrix                                    */
+
+typedef struct helm_s helm_t;
+
+typedef struct {
+    int dim;     /* 2 or 3                                                  */
+    int elem;    /* HELM_P1_TRI_RIGHT (dim 2) or HELM_Q1_HEX (dim 3)         */
+    int n;       /* cells per side on the finest mesh, >= 2                  */
+    int levels;  /* multigrid levels >= 1; n divisible by 2^(levels-1) and
+                    the coarsest mesh n/2^(levels-1) >= 1                    */
+} helm_mesh;
+
+typedef struct {
+    /* Bit f set means face f carries u = 0 (Dirichlet) instead of the
+       Sommerfeld condition: x0=1, x1=2, y0=4, y1=8, z0=16, z1=32.
+       This build implements Sommerfeld on every face: any set bit gives
+       HELM_ENOTSUP. */
+    unsigned dirichlet_faces;
+} helm_bc;
+
+typedef struct {
+    int    precision;  /* HELM_FP64 (default) or HELM_FP32_MG               */
+    int    nu1, nu2;   /* pre/post Jacobi sweeps; this build needs 2, 2      */
+    double omega;      /* Jacobi damping, default 2/3                        */
+    int    hss_m;      /* m in m*ceil(k) HSS steps, default 1                */
+    int    hss_steps;  /* if > 0, overrides m*ceil(k)                        */
+    int    restart;    /* FGMRES basis size; 0 = 3*ceil(k) + 30, max 2000    */
+    int    max_outer;  /* outer iteration cap; 0 = 4 * restart               */
+    int    x0_given;   /* 1: x holds the initial guess on entry, else x0 = 0 */
+} helm_opts;
+
+typedef struct {
+    int    outer_its;            /* FGMRES iterations (max over columns)     */
+    int    restarts;             /* restart cycles performed                 */
+    int    hss_steps;            /* HSS steps per preconditioner application */
+    long long vcycles;           /* V-cycles applied, summed over columns    */
+    int    converged;            /* 1 if every column met the tolerance      */
+    double arnoldi_rel_residual; /* max over columns, last Arnoldi estimate  */
+    double true_rel_residual;    /* max over columns of ||b - B x|| / ||b||,
+                                    recomputed in FP64 after convergence     */
+    double solve_ms;             /* wall time of helm_solve                  */
+    double precond_ms;           /* device time inside the preconditioner    */
+} helm_stats;
+
+/* Fill *opts with the defaults listed above. */
+void helm_opts_default(helm_opts* opts);
+
+/* Name of a status code (static string). */
+const char* helm_strerror(int status);
+
+/* Detail of the last HIP error seen on the calling thread ("" if none);
+ * valid until the next call on that thread. */
+const char* helm_last_error(void);
+
+/*
+ * Build a solver for one mesh and parameter set.
+ *   k > 0, delta >= 0, delta_hat > delta: the problem and the shift
+ *     (Sec. 2 and Sec. 4; delta_hat > delta as in the shift-preconditioning
+ *     iteration of Sec. 4).
+ *   bc: NULL means Sommerfeld on every face.
+ *   opts: NULL means helm_opts_default.
+ *   hip_stream: a hipStream_t (NULL = the null stream), owned by the caller.
+ * Builds the level table (n_l = n / 2^l), the per-level operator
+ * coefficients, and the coarsest-mesh FP64 inverse of L (host LU, uploaded
+ * once).  The handle owns only these (kilobytes to a few MB); solve-time
+ * vectors live in the caller's workspace.
+ * Errors: HELM_EINVAL for dim not in {2,3}, elem/dim mismatch, n < 2,
+ * levels < 1, n not divisible by 2^(levels-1), k <= 0, delta < 0,
+ * delta_hat <= delta, hss_m < 1, omega not in (0, 2), out == NULL, or a
+ * coarsest mesh with more than 4096 nodes; HELM_ENOTSUP for Dirichlet
+ * faces or (nu1, nu2) != (2, 2); HELM_ENOMEM; HELM_EDEVICE.
+ * On error *out is set to NULL and nothing is leaked.
+ */
+int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
+                const helm_bc* bc, const helm_opts* opts, void* hip_stream,
+                helm_t** out);
+
+/* Release the handle (NULL is accepted). Synchronises its stream first. */
+int helm_destroy(helm_t* h);
+
+/* Number of nodes N on the finest mesh, and on level l (0 = finest). */
+long long helm_nodes(const helm_t* h, int level);
+
+/*
+ * Bytes of device workspace helm_solve / helm_precondition / helm_vcycle
+ * need for nrhs columns (256-byte aligned base required).  nrhs >= 1.
+ */
+int helm_workspace_bytes(const helm_t* h, int nrhs, size_t* bytes);
+
+/*
+ * Solve B_delta x = rhs for nrhs columns (B_0 when delta = 0), to
+ * ||rhs - B x||_2 <= tol ||rhs||_2 per column (Sec. 5.1's relative
+ * tolerance; the true residual is recomputed in FP64 at the end).
+ *   rhs, x: device, complex FP64 [nrhs][N]; rhs is an assembled load vector
+ *     (the preconditioner maps the dual space to the primal space,
+ *     Sec. 4), e.g. from helm_load_nodal.
+ *   workspace: device, helm_workspace_bytes(h, nrhs) bytes.
+ *   stats: may be NULL.
+ * Returns HELM_OK, or HELM_ENOCONV with x holding the last iterate when
+ * max_outer is reached; HELM_EINVAL for tol not in (0, 1), nrhs < 1, NULL
+ * pointers, or a non-finite rhs norm.  A zero column gives x = 0.
+ */
+int helm_solve(helm_t* h, const void* rhs, void* x, int nrhs, double tol,
+               void* workspace, helm_stats* stats);
+
+/*
+ * b = M f for nodal source values f (real FP64 [nrhs][N]): the load vector
+ * of the nodal interpolant of f.  b: device complex FP64 [nrhs][N].
+ */
+int helm_load_nodal(helm_t* h, const double* f_nodal, void* b, int nrhs);
+
+/* ---- the steps of the hot path, exposed one by one ----------------------
+ * prec selects the vector type of x/y/b arguments: HELM_FP64 (double2) or
+ * HELM_FP32_MG (float2).  Level l meshes have n / 2^l cells per side.
+ * These calls only enqueue work on the handle's stream.
+ */
+
+/* y = Op x on level l (Op one of HELM_OP_*), matrix-free. */
+int helm_apply(helm_t* h, int op, int level, int prec,
+               const void* x, void* y, int nrhs);
+
+/* HSS residual of the correction form of eq. (HSSpc primal) on level 0:
+ * rho = (2k/(k+1)) (R - B_shift u).  u == NULL means u = 0. */
+int helm_hss_residual(helm_t* h, int prec, const void* R, const void* u,
+                      void* rho, int nrhs);
+
+/* One scaled-Jacobi sweep for L on level l (D = diag L):
+ * x_out = x_in + omega D^{-1} (b - L x_in); x_in == NULL means x_in = 0.
+ * x_out must not alias x_in or b. */
+int helm_jacobi(helm_t* h, int level, int prec, const void* x_in,
+                const void* b, void* x_out, int nrhs);
+
+/* Residual restriction: b_c = P^T (b - L x) from level l to level l+1. */
+int helm_restrict_residual(helm_t* h, int level, int prec, const void* x,
+                           const void* b, void* b_coarse, int nrhs);
+
+/* Prolongation and correction: x += P e_c from level l+1 to level l. */
+int helm_prolong_correct(helm_t* h, int level, int prec, const void* e_coarse,
+                         void* x, int nrhs);
+
+/* Coarsest-mesh solve x = L_c^{-1} b in FP64 arithmetic whatever prec. */
+int helm_coarse_solve(helm_t* h, int prec, const void* b, void* x, int nrhs);
+
+/* One V(nu1, nu2) cycle for L on level 0 with zero initial guess. */
+int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs,
+                void* workspace);
+
+/* Shifted-HSS preconditioner z = B~^{-1} v (Definition "Shifted HSS
+ * iteration for the primal system"), correction form, in the handle's
+ * precision mode.  v, z: complex FP64 [nrhs][N]. */
+int helm_precondition(helm_t* h, const void* v, void* z, int nrhs,
+                      void* workspace);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */

@@ -1,0 +1,1017 @@
+// libhelm: host driver and C ABI (include/helm.h).
+//
+// The solve is right-preconditioned flexible GMRES on B_0 in complex FP64
+// (Saad's FGMRES; the paper's outer Krylov method, Sec. 5.1) with classical
+// Gram-Schmidt applied twice for the Arnoldi step and Givens rotations on
+// the host.  The preconditioner is the shifted-HSS iteration of Sec. 4
+// (Definition "Shifted HSS iteration for the primal system") in correction
+// form
+//     u_{s+1} = u_s + V( (2k/(k+1)) (R - B_dh u_s) ),   u_0 = 0,
+// s = 0 .. m ceil(k) - 1, where V is one V(2,2) cycle for
+//     L = K + (dh^2 - k^2 - 2i dh k^2) M + (dh - i k^2) M_Gamma
+// (the left-hand side of eq. (HSSpc primal)); with exact inner solves this
+// equals the literal two-term form of the definition.  The cycle uses
+// omega-scaled Jacobi (D = diag L), FE interpolation P and P^T between
+// nested meshes (n_l = n / 2^l), and a dense FP64 inverse of L on the
+// coarsest mesh.  In HELM_FP32_MG mode the HSS iterate, the cycle and its
+// smoothers run in complex FP32; the preconditioned directions are stored
+// in FP32 and promoted exactly when FGMRES uses them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/helm.h"
+#include "launch.h"
+#include "stencil_rows.h"
+
+using namespace helm;
+using zd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DevErr {
+    hipError_t e;
+};
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            g_last_error = std::string(#expr) + ": " + hipGetErrorString(_e);          \
+            throw DevErr{_e};                                                          \
+        }                                                                              \
+    } while (0)
+
+struct Coef {
+    zd a, b, c;  // operator = a K + b M + c M_Gamma
+};
+
+// (a, b, c) of the named operators (HELM_OP_*).  B_delta from the primal
+// form of Sec. 2: (-delta + ik)^2 M - (-delta + ik) M_Gamma; L and N from
+// eq. (HSSpc primal); H from the H_primal inner product of Sec. 3.1.
+Coef op_coef(int op, double k, double delta, double dh) {
+    const zd I(0.0, 1.0);
+    auto bdelta = [&](double d) {
+        zd s = -d + I * k;
+        return Coef{1.0, s * s, -s};
+    };
+    switch (op) {
+        case HELM_OP_B0: return bdelta(0.0);
+        case HELM_OP_BDELTA: return bdelta(delta);
+        case HELM_OP_BSHIFT: return bdelta(dh);
+        case HELM_OP_L: return Coef{1.0, dh * dh - k * k - 2.0 * I * dh * k * k, dh - I * k * k};
+        case HELM_OP_N: return Coef{-1.0, k * k - dh * dh - 2.0 * I * dh * k * k, -dh - I * k * k};
+        case HELM_OP_H: return Coef{0.0, 2.0 * dh * k, k};
+        case HELM_OP_M: return Coef{0.0, 1.0, 0.0};
+    }
+    return Coef{0.0, 0.0, 0.0};
+}
+
+template <typename T>
+cx<T> tocx(zd z) { return mk((T)z.real(), (T)z.imag()); }
+
+template <typename T>
+Op2<T> make_op2(const Coef& cf, int n, double omega) {
+    const double h = 1.0 / n;
+    const zd A = cf.a, Bm = cf.b * (h * h / 24.0), Cg = cf.c * (h / 6.0);
+    const zd wC = 4.0 * A + 12.0 * Bm, wAx = -A + 2.0 * Bm, wDg = 2.0 * Bm;
+    Op2<T> o;
+    o.A = tocx<T>(A);
+    o.Bm = tocx<T>(Bm);
+    o.Cg = tocx<T>(Cg);
+    o.wC = tocx<T>(wC);
+    o.wAx = tocx<T>(wAx);
+    o.wDg = tocx<T>(wDg);
+    o.odC = tocx<T>(omega / wC);
+    o.omega = (T)omega;
+    o.n = n;
+    return o;
+}
+
+template <typename T>
+Op3<T> make_op3(const Coef& cf, int n, double omega) {
+    const double h = 1.0 / n;
+    Op3<T> o;
+    o.a = tocx<T>(cf.a);
+    o.b = tocx<T>(cf.b);
+    o.c = tocx<T>(cf.c);
+    o.h = (T)h;
+    o.omega = (T)omega;
+    o.n = n;
+    // interior weights by neighbour class (number of nonzero offsets)
+    Op3<double> od;
+    od.a = tocx<double>(cf.a);
+    od.b = tocx<double>(cf.b);
+    od.c = tocx<double>(cf.c);
+    od.h = h;
+    od.n = n;
+    Line3<double> f = line_factors<double>(1, 2, h);
+    for (int cls = 0; cls < 4; ++cls) {
+        int dx = cls >= 1 ? 1 : 0, dy = cls >= 2 ? 1 : 0, dz = cls >= 3 ? 1 : 0;
+        cxd w = weight3(od, f, f, f, dx, dy, dz);
+        o.wInt[cls] = mk((T)w.x, (T)w.y);
+    }
+    cxd wc = weight3(od, f, f, f, 0, 0, 0);
+    zd dC(wc.x, wc.y);
+    o.odC = tocx<T>(omega / dC);
+    return o;
+}
+
+// In-place inverse of a dense complex matrix by Gauss-Jordan elimination
+// with partial pivoting.  Returns false if singular.
+bool invert_dense(std::vector<zd>& A, int n) {
+    std::vector<zd> inv((size_t)n * n, zd(0.0));
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        double best = std::abs(A[(size_t)col * n + col]);
+        for (int r = col + 1; r < n; ++r) {
+            double v = std::abs(A[(size_t)r * n + col]);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (best == 0.0) return false;
+        if (piv != col) {
+            for (int c = 0; c < n; ++c) {
+                std::swap(A[(size_t)piv * n + c], A[(size_t)col * n + c]);
+                std::swap(inv[(size_t)piv * n + c], inv[(size_t)col * n + c]);
+            }
+        }
+        const zd d = 1.0 / A[(size_t)col * n + col];
+        for (int c = 0; c < n; ++c) {
+            A[(size_t)col * n + c] *= d;
+            inv[(size_t)col * n + c] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const zd f = A[(size_t)r * n + col];
+            if (f == 0.0) continue;
+            for (int c = 0; c < n; ++c) {
+                A[(size_t)r * n + c] -= f * A[(size_t)col * n + c];
+                inv[(size_t)r * n + c] -= f * inv[(size_t)col * n + c];
+            }
+        }
+    }
+    A.swap(inv);
+    return true;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle --
+struct helm_s {
+    int dim = 2, elem = HELM_P1_TRI_RIGHT, n = 0, levels = 1;
+    double k = 0, delta = 0, dh = 0;
+    helm_opts opts{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int hss_steps = 0, restart = 0, max_outer = 0;
+    std::vector<int> nl;
+    std::vector<long long> Nl;
+    cxd* d_cinv = nullptr;  // coarsest-mesh inverse of L, FP64
+    int nc = 0;             // coarsest-mesh node count
+    int prec = HELM_FP64;
+    double omega = 2.0 / 3.0;
+
+    Coef coef(int op) const { return op_coef(op, k, delta, dh); }
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t mg_b[32], mg_x[32], mg_t[32];
+    size_t R, u;
+    size_t V, Z;
+    size_t dh, dh2, dnorm, part, npart, dy, cols;
+    size_t total;
+};
+
+Layout layout(const helm_t* h, int nrhs) {
+    Layout L{};
+    size_t off = 0;
+    const size_t smg = h->prec == HELM_FP64 ? sizeof(cxd) : sizeof(cxf);
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += up(bytes);
+        return o;
+    };
+    const int R = h->restart;
+    const long long N = h->Nl[0];
+    const int nblk = multidot_blocks(N);
+    L.cols = take(sizeof(int) * nrhs);
+    L.dh = take(sizeof(cxd) * nrhs * (R + 1));
+    L.dh2 = take(sizeof(cxd) * nrhs * (R + 1));
+    L.dnorm = take(sizeof(double) * nrhs);
+    L.dy = take(sizeof(cxd) * nrhs * R);
+    L.part = take(sizeof(cxd) * (size_t)nrhs * (R + 1) * nblk);
+    L.npart = take(sizeof(double) * (size_t)nrhs * nblk);
+    for (int l = 0; l < h->levels; ++l) {
+        L.mg_b[l] = take(smg * nrhs * h->Nl[l]);
+        L.mg_x[l] = take(smg * nrhs * h->Nl[l]);
+        L.mg_t[l] = take(smg * nrhs * h->Nl[l]);
+    }
+    L.R = take(smg * nrhs * N);
+    L.u = take(smg * nrhs * N);
+    L.V = take(sizeof(cxd) * (size_t)nrhs * (R + 1) * N);
+    L.Z = take(smg * (size_t)nrhs * R * N);
+    L.total = off;
+    return L;
+}
+
+template <typename V>
+Vec<V> at_ws(void* ws, size_t off, long long cstride) {
+    return Vec<V>{reinterpret_cast<V*>(static_cast<char*>(ws) + off), cstride, 0, nullptr};
+}
+
+template <typename V>
+Vec<const V> cst(Vec<V> v) {
+    return Vec<const V>{v.base, v.cstride, v.off, v.cols};
+}
+
+// ---------------------------------------------------------------- levels --
+template <typename T>
+void apply_mode(helm_t* h, int op, int l, int mode, T s, Vec<const cx<T>> X, Vec<const cx<T>> B,
+                Vec<cx<T>> Y, int ns) {
+    const Coef cf = h->coef(op);
+    if (h->dim == 2) {
+        stencil2d<T, T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns);
+    } else {
+        stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns);
+    }
+}
+
+template <typename T>
+void resid_restrict(helm_t* h, int l, Vec<const cx<T>> X, Vec<const cx<T>> B, Vec<cx<T>> Bc,
+                    Vec<cx<T>> tmp, int ns) {
+    const Coef cf = h->coef(HELM_OP_L);
+    if (h->dim == 2) {
+        resid_restrict2d<T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
+    } else {
+        stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), MODE_RESID, (T)1, X, B,
+                        tmp, ns);
+        restrict3d<T>(h->stream, h->nl[l], cst(tmp), Bc, ns);
+    }
+}
+
+template <typename T>
+void prolong(helm_t* h, int l, Vec<const cx<T>> E, Vec<cx<T>> X, int ns) {
+    if (h->dim == 2) prolong2d<T>(h->stream, h->nl[l], E, X, ns);
+    else prolong3d<T>(h->stream, h->nl[l], E, X, ns);
+}
+
+// One V(2,2) cycle on level l for L x = b with zero initial guess; the
+// result is left in x.  Level buffers b, x, t of levels > l come from ws.
+template <typename T>
+void vcycle(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cx<T>> b, Vec<cx<T>> x,
+            Vec<cx<T>> t, int ns) {
+    if (l == h->levels - 1) {
+        coarse_apply<T>(h->stream, h->d_cinv, h->nc, b, x, ns);
+        return;
+    }
+    const T one = (T)1;
+    // pre-smoothing: t = omega D^{-1} b, x = t + omega D^{-1} (b - L t)
+    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI0, one, Vec<const cx<T>>{}, b, t, ns);
+    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, cst(t), b, x, ns);
+    const long long Nc = h->Nl[l + 1];
+    Vec<cx<T>> bc = at_ws<cx<T>>(ws, Lw.mg_b[l + 1], Nc);
+    Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
+    Vec<cx<T>> tc = at_ws<cx<T>>(ws, Lw.mg_t[l + 1], Nc);
+    resid_restrict<T>(h, l, cst(x), b, bc, t, ns);
+    vcycle<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
+    prolong<T>(h, l, cst(xc), x, ns);
+    // post-smoothing: t = J(x), x = J(t)
+    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, cst(x), b, t, ns);
+    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, cst(t), b, x, ns);
+}
+
+template <typename T>
+__global__ void k_zero(cx<T>* p, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = mk((T)0, (T)0);
+}
+
+template <typename T>
+void zero(hipStream_t st, cx<T>* p, long long n) {
+    if (n <= 0) return;
+    k_zero<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n);
+}
+
+// Shifted-HSS preconditioner on the slot-major buffers R -> u (precision T).
+template <typename T>
+void hss_loop(helm_t* h, const Layout& Lw, void* ws, int ns) {
+    const long long N = h->Nl[0];
+    Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, N);
+    Vec<cx<T>> u = at_ws<cx<T>>(ws, Lw.u, N);
+    Vec<cx<T>> rho = at_ws<cx<T>>(ws, Lw.mg_b[0], N);
+    Vec<cx<T>> e = at_ws<cx<T>>(ws, Lw.mg_x[0], N);
+    Vec<cx<T>> t = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
+    const T c = (T)(2.0 * h->k / (h->k + 1.0));
+    zero<T>(h->stream, u.base, N * ns);
+    for (int s = 0; s < h->hss_steps; ++s) {
+        apply_mode<T>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c, cst(u), cst(R), rho, ns);
+        vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns);
+        axpy1<T>(h->stream, N, cst(e), u, ns);
+    }
+}
+
+// z = B~^{-1} v for ns slots: v and z addressed through Vec descriptors
+// (FP64 v; z in the mode's storage type).
+template <typename T>
+void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<cx<T>> z, int ns) {
+    const long long N = h->Nl[0];
+    copy_cast<T, double>(h->stream, N, v, at_ws<cx<T>>(ws, Lw.R, N), ns);
+    hss_loop<T>(h, Lw, ws, ns);
+    copy_cast<T, T>(h->stream, N, cst(at_ws<cx<T>>(ws, Lw.u, N)), z, ns);
+}
+
+// ----------------------------------------------------------------- FGMRES --
+struct ColState {
+    std::vector<zd> H;  // (R+1) x R column-major: H[i + j*(R+1)]
+    std::vector<zd> cs, sn, g;
+    double bnorm = 0.0, beta = 0.0, est = 0.0;
+    int its = 0;
+    bool done = false;
+};
+
+template <typename T>
+int fgmres(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws, helm_stats* st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = h->stream;
+    const long long N = h->Nl[0];
+    const int R = h->restart;
+    const Layout Lw = layout(h, nrhs);
+    char* wsb = static_cast<char*>(ws);
+    int* d_cols = reinterpret_cast<int*>(wsb + Lw.cols);
+    cxd* d_h = reinterpret_cast<cxd*>(wsb + Lw.dh);
+    cxd* d_h2 = reinterpret_cast<cxd*>(wsb + Lw.dh2);
+    double* d_norm = reinterpret_cast<double*>(wsb + Lw.dnorm);
+    cxd* d_part = reinterpret_cast<cxd*>(wsb + Lw.part);
+    double* d_npart = reinterpret_cast<double*>(wsb + Lw.npart);
+    cxd* d_y = reinterpret_cast<cxd*>(wsb + Lw.dy);
+    cxd* Vb = reinterpret_cast<cxd*>(wsb + Lw.V);
+    cx<T>* Zb = reinterpret_cast<cx<T>*>(wsb + Lw.Z);
+    const int nblk = multidot_blocks(N);
+    const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
+    const Op2<double> B2 = make_op2<double>(b0, h->n, h->omega);
+    const Op3<double> B3 = make_op3<double>(b0, h->n, h->omega);
+
+    // V[c][i] at Vb + (c*(R+1) + i)*N ; Z[c][i] at Zb + (c*R + i)*N
+    auto Vcol = [&](int i, const int* cols) {
+        return Vec<cxd>{Vb, (long long)(R + 1) * N, (long long)i * N, cols};
+    };
+    auto Zcol = [&](int i, const int* cols) {
+        return Vec<cx<T>>{Zb, (long long)R * N, (long long)i * N, cols};
+    };
+    auto Xcol = [&](const int* cols) { return Vec<cxd>{x, N, 0, cols}; };
+    auto Bcol = [&](const int* cols) { return Vec<const cxd>{rhs, N, 0, cols}; };
+    auto apply_B = [&](int mode, Vec<const cxd> X, Vec<const cxd> Bv, Vec<cxd> Y, int ns) {
+        if (h->dim == 2) stencil2d<double, double>(s, B2, mode, 1.0, X, Bv, Y, ns);
+        else stencil3d<double, double>(s, B3, mode, 1.0, X, Bv, Y, ns);
+    };
+    auto apply_BZ = [&](Vec<const cx<T>> Zv, Vec<cxd> Y, int ns) {
+        if (h->dim == 2) stencil2d<double, T>(s, B2, MODE_APPLY, 1.0, Zv, Vec<const cxd>{}, Y, ns);
+        else stencil3d<double, T>(s, B3, MODE_APPLY, 1.0, Zv, Vec<const cxd>{}, Y, ns);
+    };
+
+    std::vector<ColState> cs(nrhs);
+    std::vector<int> all(nrhs);
+    for (int c = 0; c < nrhs; ++c) all[c] = c;
+    HIPCHK(hipMemcpyAsync(d_cols, all.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    // ||b|| per column
+    norm2(s, N, Bcol(d_cols), d_npart, d_norm, 1, nrhs);
+    std::vector<double> hn(nrhs);
+    HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int c = 0; c < nrhs; ++c) {
+        if (!std::isfinite(hn[c])) {
+            g_last_error = "non-finite right-hand side";
+            return HELM_EINVAL;
+        }
+        cs[c].bnorm = hn[c];
+        cs[c].H.assign((size_t)(R + 1) * R, 0.0);
+        cs[c].cs.assign(R, 0.0);
+        cs[c].sn.assign(R, 0.0);
+        cs[c].g.assign(R + 1, 0.0);
+    }
+    if (!h->opts.x0_given) zero<double>(s, x, N * nrhs);
+
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double precond_ms = 0.0;
+    int restarts = 0;
+    long long vcycles = 0;
+    int total_its = 0;
+    std::vector<int> active;
+    std::vector<int> host_cols(nrhs);
+    bool first_cycle = true;
+
+    auto finish_cols = [&](const std::vector<int>& cols_done, int m) {
+        // x_c += Z_c y_c for the listed columns, with y from the triangular solve
+        if (cols_done.empty() || m == 0) return;
+        std::vector<cxd> yb((size_t)cols_done.size() * R);
+        for (size_t q = 0; q < cols_done.size(); ++q) {
+            ColState& C = cs[cols_done[q]];
+            std::vector<zd> y(m);
+            for (int i = m - 1; i >= 0; --i) {
+                zd acc = C.g[i];
+                for (int jj = i + 1; jj < m; ++jj) acc -= C.H[i + (size_t)jj * (R + 1)] * y[jj];
+                y[i] = acc / C.H[i + (size_t)i * (R + 1)];
+            }
+            for (int i = 0; i < m; ++i) yb[q * R + i] = mk(y[i].real(), y[i].imag());
+        }
+        int* d_c2 = d_cols;  // reuse: upload the finishing set
+        HIPCHK(hipMemcpyAsync(d_c2, cols_done.data(), sizeof(int) * cols_done.size(),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_y, yb.data(), sizeof(cxd) * yb.size(), hipMemcpyHostToDevice, s));
+        update_solution<T>(s, N, m, cst(Zcol(0, d_c2)), d_y, R, Xcol(d_c2), (int)cols_done.size());
+        HIPCHK(hipStreamSynchronize(s));
+    };
+
+    for (;;) {
+        // ---- (re)start: r = b - B x for unconverged columns, V_0 = r/||r||
+        active.clear();
+        for (int c = 0; c < nrhs; ++c)
+            if (!cs[c].done && cs[c].its < h->max_outer) active.push_back(c);
+        if (active.empty()) break;
+        int ns = (int)active.size();
+        HIPCHK(hipMemcpyAsync(d_cols, active.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+        if (first_cycle && !h->opts.x0_given) {
+            copy_cast<double, double>(s, N, Bcol(d_cols), Vcol(0, d_cols), ns);
+        } else {
+            apply_B(MODE_RESID, cst(Xcol(d_cols)), Bcol(d_cols), Vcol(0, d_cols), ns);
+        }
+        norm2(s, N, cst(Vcol(0, d_cols)), d_npart, d_norm, 1, ns);
+        HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        {
+            std::vector<int> still;
+            for (int q = 0; q < ns; ++q) {
+                ColState& C = cs[active[q]];
+                C.beta = hn[q];
+                C.est = C.bnorm > 0 ? hn[q] / C.bnorm : 0.0;
+                if (C.bnorm == 0.0 || hn[q] <= tol * C.bnorm) {
+                    C.done = true;
+                } else {
+                    still.push_back(active[q]);
+                }
+            }
+            if (still.empty()) break;
+            if (!first_cycle) ++restarts;
+            first_cycle = false;
+            // scale V_0 of the still-active columns: order norms as `still`
+            std::vector<double> bn;
+            for (int c : still) bn.push_back(cs[c].beta);
+            active = still;
+            ns = (int)active.size();
+            HIPCHK(hipMemcpyAsync(d_cols, active.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_norm, bn.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+            scale_inv(s, N, cst(Vcol(0, d_cols)), Vcol(0, d_cols), d_norm, 1, ns);
+            for (int c : active) {
+                ColState& C = cs[c];
+                std::fill(C.g.begin(), C.g.end(), zd(0.0));
+                C.g[0] = C.beta;
+            }
+        }
+        int m_done = 0;
+        for (int j = 0; j < R; ++j) {
+            ns = (int)active.size();
+            // z_j = B~^{-1} v_j
+            HIPCHK(hipEventRecord(e0, s));
+            precondition<T>(h, Lw, ws, cst(Vcol(j, d_cols)), Zcol(j, d_cols), ns);
+            HIPCHK(hipEventRecord(e1, s));
+            vcycles += (long long)ns * h->hss_steps;
+            // w = B z_j into V_{j+1}
+            apply_BZ(cst(Zcol(j, d_cols)), Vcol(j + 1, d_cols), ns);
+            // classical Gram-Schmidt, twice
+            for (int pass = 0; pass < 2; ++pass) {
+                cxd* hd = pass == 0 ? d_h : d_h2;
+                multidot(s, N, j + 1, cst(Vcol(0, d_cols)), cst(Vcol(j + 1, d_cols)), d_part, ns);
+                reduce_parts(s, j + 1, nblk, d_part, hd, R + 1, 0, ns);
+                multi_axpy(s, N, j + 1, cst(Vcol(0, d_cols)), hd, R + 1, Vcol(j + 1, d_cols), ns);
+            }
+            norm2(s, N, cst(Vcol(j + 1, d_cols)), d_npart, d_norm, 1, ns);
+            scale_inv(s, N, cst(Vcol(j + 1, d_cols)), Vcol(j + 1, d_cols), d_norm, 1, ns);
+            std::vector<cxd> hh((size_t)ns * (R + 1)), hh2((size_t)ns * (R + 1));
+            HIPCHK(hipMemcpyAsync(hh.data(), d_h, sizeof(cxd) * ns * (R + 1), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(hh2.data(), d_h2, sizeof(cxd) * ns * (R + 1), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            precond_ms += ms;
+            ++total_its;
+            m_done = j + 1;
+            std::vector<int> conv, keep;
+            for (int q = 0; q < ns; ++q) {
+                ColState& C = cs[active[q]];
+                zd* Hc = &C.H[(size_t)j * (R + 1)];
+                for (int i = 0; i <= j; ++i) {
+                    const cxd a = hh[(size_t)q * (R + 1) + i], b = hh2[(size_t)q * (R + 1) + i];
+                    Hc[i] = zd(a.x + b.x, a.y + b.y);
+                }
+                Hc[j + 1] = hn[q];
+                for (int i = 0; i < j; ++i) {
+                    const zd t = C.cs[i] * Hc[i] + C.sn[i] * Hc[i + 1];
+                    Hc[i + 1] = -std::conj(C.sn[i]) * Hc[i] + std::conj(C.cs[i]) * Hc[i + 1];
+                    Hc[i] = t;
+                }
+                const zd a = Hc[j], b = Hc[j + 1];
+                const double den = std::sqrt(std::norm(a) + std::norm(b));
+                C.cs[j] = den != 0.0 ? std::conj(a) / den : zd(1.0);
+                C.sn[j] = den != 0.0 ? std::conj(b) / den : zd(0.0);
+                Hc[j] = C.cs[j] * a + C.sn[j] * b;
+                Hc[j + 1] = 0.0;
+                C.g[j + 1] = -std::conj(C.sn[j]) * C.g[j];
+                C.g[j] = C.cs[j] * C.g[j];
+                C.its += 1;
+                C.est = std::abs(C.g[j + 1]) / C.bnorm;
+                const bool breakdown = hn[q] == 0.0;
+                if (std::abs(C.g[j + 1]) <= tol * C.bnorm || C.its >= h->max_outer || breakdown)
+                    conv.push_back(active[q]);
+                else
+                    keep.push_back(active[q]);
+            }
+            if (!conv.empty()) {
+                finish_cols(conv, j + 1);
+                for (int c : conv) cs[c].done = true;  // re-verified below
+            }
+            if (keep.empty()) break;
+            if (!conv.empty()) {
+                // compact: the device h/norm buffers are slot-indexed per call
+                active = keep;
+                HIPCHK(hipMemcpyAsync(d_cols, active.data(), sizeof(int) * active.size(),
+                                      hipMemcpyHostToDevice, s));
+            }
+            if (j == R - 1) {
+                finish_cols(active, R);  // restart the rest
+            }
+        }
+        (void)m_done;
+        // columns marked done are re-checked on the true residual
+        std::vector<int> chk;
+        for (int c = 0; c < nrhs; ++c)
+            if (cs[c].done) chk.push_back(c);
+        if (!chk.empty()) {
+            const int nc = (int)chk.size();
+            HIPCHK(hipMemcpyAsync(d_cols, chk.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
+            apply_B(MODE_RESID, cst(Xcol(d_cols)), Bcol(d_cols), Vcol(0, d_cols), nc);
+            norm2(s, N, cst(Vcol(0, d_cols)), d_npart, d_norm, 1, nc);
+            HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int q = 0; q < nc; ++q) {
+                ColState& C = cs[chk[q]];
+                const double rel = C.bnorm > 0 ? hn[q] / C.bnorm : 0.0;
+                if (rel > tol && C.its < h->max_outer) C.done = false;  // restart it
+                C.est = rel;
+            }
+        }
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    // final true residuals
+    double worst = 0.0, worst_arn = 0.0;
+    int maxits = 0;
+    bool ok = true;
+    {
+        HIPCHK(hipMemcpyAsync(d_cols, all.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        apply_B(MODE_RESID, cst(Xcol(d_cols)), Bcol(d_cols), Vcol(0, d_cols), nrhs);
+        norm2(s, N, cst(Vcol(0, d_cols)), d_npart, d_norm, 1, nrhs);
+        HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < nrhs; ++c) {
+            const double rel = cs[c].bnorm > 0 ? hn[c] / cs[c].bnorm : 0.0;
+            worst = std::max(worst, rel);
+            worst_arn = std::max(worst_arn, cs[c].est);
+            maxits = std::max(maxits, cs[c].its);
+            if (!(rel <= tol)) ok = false;
+        }
+    }
+    if (st) {
+        st->outer_its = maxits;
+        st->restarts = restarts;
+        st->hss_steps = h->hss_steps;
+        st->vcycles = vcycles;
+        st->converged = ok ? 1 : 0;
+        st->arnoldi_rel_residual = worst_arn;
+        st->true_rel_residual = worst;
+        st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        st->precond_ms = precond_ms;
+    }
+    (void)total_its;
+    return ok ? HELM_OK : HELM_ENOCONV;
+}
+
+int status_from_exception() { return HELM_EDEVICE; }
+
+}  // namespace
+
+// =================================================================== C ABI ==
+extern "C" {
+
+void helm_opts_default(helm_opts* o) {
+    if (!o) return;
+    o->precision = HELM_FP64;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->omega = 2.0 / 3.0;
+    o->hss_m = 1;
+    o->hss_steps = 0;
+    o->restart = 0;
+    o->max_outer = 0;
+    o->x0_given = 0;
+}
+
+const char* helm_strerror(int status) {
+    switch (status) {
+        case HELM_OK: return "ok";
+        case HELM_EINVAL: return "invalid argument";
+        case HELM_ENOMEM: return "out of memory";
+        case HELM_EDEVICE: return "HIP device error";
+        case HELM_ENOCONV: return "not converged within max_outer";
+        case HELM_ENOTSUP: return "not supported by this build";
+    }
+    return "unknown status";
+}
+
+const char* helm_last_error(void) { return g_last_error.c_str(); }
+
+int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
+                const helm_bc* bc, const helm_opts* opts, void* hip_stream, helm_t** out) {
+    if (!out) return HELM_EINVAL;
+    *out = nullptr;
+    if (!mesh) return HELM_EINVAL;
+    helm_opts o;
+    if (opts) o = *opts; else helm_opts_default(&o);
+    if (mesh->dim != 2 && mesh->dim != 3) return HELM_EINVAL;
+    if ((mesh->dim == 2 && mesh->elem != HELM_P1_TRI_RIGHT) ||
+        (mesh->dim == 3 && mesh->elem != HELM_Q1_HEX))
+        return HELM_EINVAL;
+    if (mesh->n < 2 || mesh->levels < 1 || mesh->levels > 30) return HELM_EINVAL;
+    if (mesh->n % (1 << (mesh->levels - 1)) != 0) return HELM_EINVAL;
+    if (!(k > 0.0) || !std::isfinite(k)) return HELM_EINVAL;
+    if (!(delta >= 0.0) || !std::isfinite(delta)) return HELM_EINVAL;
+    if (!(delta_hat > delta) || !std::isfinite(delta_hat)) return HELM_EINVAL;
+    if (o.hss_m < 1 || o.hss_steps < 0) return HELM_EINVAL;
+    if (!(o.omega > 0.0 && o.omega < 2.0)) return HELM_EINVAL;
+    if (o.precision != HELM_FP64 && o.precision != HELM_FP32_MG) return HELM_EINVAL;
+    if (o.restart < 0 || o.max_outer < 0 || o.restart > 2000) return HELM_EINVAL;
+    if (bc && bc->dirichlet_faces != 0) return HELM_ENOTSUP;
+    if (o.nu1 != 2 || o.nu2 != 2) return HELM_ENOTSUP;
+    const int nc_side = mesh->n >> (mesh->levels - 1);
+    long long ncoarse = 1;
+    for (int d = 0; d < mesh->dim; ++d) ncoarse *= (nc_side + 1);
+    if (ncoarse > 4096) return HELM_EINVAL;
+
+    helm_t* h = new (std::nothrow) helm_t;
+    if (!h) return HELM_ENOMEM;
+    try {
+        h->dim = mesh->dim;
+        h->elem = mesh->elem;
+        h->n = mesh->n;
+        h->levels = mesh->levels;
+        h->k = k;
+        h->delta = delta;
+        h->dh = delta_hat;
+        h->opts = o;
+        h->prec = o.precision;
+        h->omega = o.omega;
+        h->stream = static_cast<hipStream_t>(hip_stream);
+        HIPCHK(hipGetDevice(&h->device));
+        h->hss_steps = o.hss_steps > 0 ? o.hss_steps : (int)(o.hss_m * std::ceil(k));
+        h->restart = o.restart > 0 ? o.restart : std::min(2000, 3 * (int)std::ceil(k) + 30);
+        h->max_outer = o.max_outer > 0 ? o.max_outer : 4 * h->restart;
+        for (int l = 0; l < h->levels; ++l) {
+            const int nl = h->n >> l;
+            long long Nl = 1;
+            for (int d = 0; d < h->dim; ++d) Nl *= (nl + 1);
+            h->nl.push_back(nl);
+            h->Nl.push_back(Nl);
+        }
+        // coarsest-mesh dense L (from the same stencil rows the kernels use)
+        const int ncs = h->nl.back();
+        const int nc = (int)h->Nl.back();
+        h->nc = nc;
+        std::vector<zd> A((size_t)nc * nc, zd(0.0));
+        const Coef cf = h->coef(HELM_OP_L);
+        if (h->dim == 2) {
+            const Op2<double> op = make_op2<double>(cf, ncs, h->omega);
+            const int np = ncs + 1;
+            const int di[7] = {0, 1, -1, 0, 0, 1, -1}, dj[7] = {0, 0, 0, 1, -1, 1, -1};
+            for (int j = 0; j <= ncs; ++j)
+                for (int i = 0; i <= ncs; ++i) {
+                    Row7<double> r = row_weights(op, i, j);
+                    for (int q = 0; q < 7; ++q) {
+                        const int ii = i + di[q], jj = j + dj[q];
+                        if (ii < 0 || ii > ncs || jj < 0 || jj > ncs) continue;
+                        A[(size_t)(i + np * j) * nc + (ii + np * jj)] += zd(r.w[q].x, r.w[q].y);
+                    }
+                }
+        } else {
+            const Op3<double> op = make_op3<double>(cf, ncs, h->omega);
+            const int np = ncs + 1;
+            for (int l = 0; l <= ncs; ++l)
+                for (int j = 0; j <= ncs; ++j)
+                    for (int i = 0; i <= ncs; ++i) {
+                        const Line3<double> fx = line_factors<double>(i, ncs, op.h);
+                        const Line3<double> fy = line_factors<double>(j, ncs, op.h);
+                        const Line3<double> fz = line_factors<double>(l, ncs, op.h);
+                        for (int dz = -1; dz <= 1; ++dz)
+                            for (int dy = -1; dy <= 1; ++dy)
+                                for (int dx = -1; dx <= 1; ++dx) {
+                                    const int ii = i + dx, jj = j + dy, ll = l + dz;
+                                    if (ii < 0 || ii > ncs || jj < 0 || jj > ncs || ll < 0 || ll > ncs)
+                                        continue;
+                                    const cxd w = weight3(op, fx, fy, fz, dx, dy, dz);
+                                    A[(size_t)(i + np * (j + np * l)) * nc + (ii + np * (jj + np * ll))] +=
+                                        zd(w.x, w.y);
+                                }
+                    }
+        }
+        if (!invert_dense(A, nc)) {
+            g_last_error = "singular coarsest-mesh operator";
+            delete h;
+            return HELM_EINVAL;
+        }
+        std::vector<cxd> Ah((size_t)nc * nc);
+        for (size_t q = 0; q < Ah.size(); ++q) Ah[q] = mk(A[q].real(), A[q].imag());
+        if (hipMalloc(&h->d_cinv, sizeof(cxd) * Ah.size()) != hipSuccess) {
+            delete h;
+            return HELM_ENOMEM;
+        }
+        HIPCHK(hipMemcpy(h->d_cinv, Ah.data(), sizeof(cxd) * Ah.size(), hipMemcpyHostToDevice));
+    } catch (const DevErr&) {
+        if (h->d_cinv) (void)hipFree(h->d_cinv);
+        delete h;
+        return HELM_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        if (h->d_cinv) (void)hipFree(h->d_cinv);
+        delete h;
+        return HELM_ENOMEM;
+    }
+    *out = h;
+    return HELM_OK;
+}
+
+int helm_destroy(helm_t* h) {
+    if (!h) return HELM_OK;
+    int rc = HELM_OK;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = HELM_EDEVICE;
+    if (h->d_cinv && hipFree(h->d_cinv) != hipSuccess) rc = HELM_EDEVICE;
+    delete h;
+    return rc;
+}
+
+long long helm_nodes(const helm_t* h, int level) {
+    if (!h || level < 0 || level >= h->levels) return -1;
+    return h->Nl[level];
+}
+
+int helm_workspace_bytes(const helm_t* h, int nrhs, size_t* bytes) {
+    if (!h || !bytes || nrhs < 1) return HELM_EINVAL;
+    *bytes = layout(h, nrhs).total;
+    return HELM_OK;
+}
+
+int helm_solve(helm_t* h, const void* rhs, void* x, int nrhs, double tol, void* workspace,
+               helm_stats* stats) {
+    if (!h || !rhs || !x || !workspace || nrhs < 1) return HELM_EINVAL;
+    if (!(tol > 0.0 && tol < 1.0)) return HELM_EINVAL;
+    try {
+        if (h->prec == HELM_FP64)
+            return fgmres<double>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x), nrhs, tol,
+                                  workspace, stats);
+        return fgmres<float>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x), nrhs, tol,
+                             workspace, stats);
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        return HELM_ENOMEM;
+    }
+}
+
+int helm_load_nodal(helm_t* h, const double* f_nodal, void* b, int nrhs) {
+    if (!h || !f_nodal || !b || nrhs < 1) return HELM_EINVAL;
+    const long long N = h->Nl[0];
+    cxd* tmp = nullptr;
+    try {
+        HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(cxd) * N * nrhs, h->stream));
+        real_to_complex(h->stream, N, f_nodal, tmp, nrhs);
+        apply_mode<double>(h, HELM_OP_M, 0, MODE_APPLY, 1.0, Vec<const cxd>{tmp, N, 0, nullptr},
+                           Vec<const cxd>{}, Vec<cxd>{static_cast<cxd*>(b), N, 0, nullptr}, nrhs);
+        HIPCHK(hipFreeAsync(tmp, h->stream));
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+#define PREC_DISPATCH(prec, CALL_D, CALL_F) \
+    ((prec) == HELM_FP64 ? (CALL_D) : (CALL_F))
+
+int helm_apply(helm_t* h, int op, int level, int prec, const void* x, void* y, int nrhs) {
+    if (!h || !x || !y || nrhs < 1 || level < 0 || level >= h->levels) return HELM_EINVAL;
+    if (op < HELM_OP_B0 || op > HELM_OP_M) return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    const long long N = h->Nl[level];
+    try {
+        if (prec == HELM_FP64)
+            apply_mode<double>(h, op, level, MODE_APPLY, 1.0,
+                               Vec<const cxd>{static_cast<const cxd*>(x), N, 0, nullptr},
+                               Vec<const cxd>{}, Vec<cxd>{static_cast<cxd*>(y), N, 0, nullptr}, nrhs);
+        else
+            apply_mode<float>(h, op, level, MODE_APPLY, 1.0f,
+                              Vec<const cxf>{static_cast<const cxf*>(x), N, 0, nullptr},
+                              Vec<const cxf>{}, Vec<cxf>{static_cast<cxf*>(y), N, 0, nullptr}, nrhs);
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+extern "C++" {
+template <typename T>
+static void hss_residual_t(helm_t* h, const void* R, const void* u, void* rho, int nrhs) {
+    const long long N = h->Nl[0];
+    const T c = (T)(2.0 * h->k / (h->k + 1.0));
+    Vec<const cx<T>> Rv{static_cast<const cx<T>*>(R), N, 0, nullptr};
+    Vec<cx<T>> out{static_cast<cx<T>*>(rho), N, 0, nullptr};
+    if (u) {
+        apply_mode<T>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c,
+                      Vec<const cx<T>>{static_cast<const cx<T>*>(u), N, 0, nullptr}, Rv, out, nrhs);
+    } else {
+        // u = 0: rho = c R, through the residual kernel on a zero vector
+        cx<T>* tmp = nullptr;
+        HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(cx<T>) * N * nrhs, h->stream));
+        zero<T>(h->stream, tmp, N * nrhs);
+        apply_mode<T>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c, Vec<const cx<T>>{tmp, N, 0, nullptr}, Rv,
+                      out, nrhs);
+        HIPCHK(hipFreeAsync(tmp, h->stream));
+    }
+}
+}  // extern "C++"
+
+int helm_hss_residual(helm_t* h, int prec, const void* R, const void* u, void* rho, int nrhs) {
+    if (!h || !R || !rho || nrhs < 1) return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    try {
+        if (prec == HELM_FP64) hss_residual_t<double>(h, R, u, rho, nrhs);
+        else hss_residual_t<float>(h, R, u, rho, nrhs);
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+int helm_jacobi(helm_t* h, int level, int prec, const void* x_in, const void* b, void* x_out,
+                int nrhs) {
+    if (!h || !b || !x_out || nrhs < 1 || level < 0 || level >= h->levels) return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    if (x_out == x_in || x_out == b) return HELM_EINVAL;
+    const long long N = h->Nl[level];
+    const int mode = x_in ? MODE_JACOBI : MODE_JACOBI0;
+    try {
+        if (prec == HELM_FP64)
+            apply_mode<double>(h, HELM_OP_L, level, mode, 1.0,
+                               Vec<const cxd>{static_cast<const cxd*>(x_in), N, 0, nullptr},
+                               Vec<const cxd>{static_cast<const cxd*>(b), N, 0, nullptr},
+                               Vec<cxd>{static_cast<cxd*>(x_out), N, 0, nullptr}, nrhs);
+        else
+            apply_mode<float>(h, HELM_OP_L, level, mode, 1.0f,
+                              Vec<const cxf>{static_cast<const cxf*>(x_in), N, 0, nullptr},
+                              Vec<const cxf>{static_cast<const cxf*>(b), N, 0, nullptr},
+                              Vec<cxf>{static_cast<cxf*>(x_out), N, 0, nullptr}, nrhs);
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+extern "C++" {
+template <typename T>
+static void restrict_t(helm_t* h, int level, const void* x, const void* b, void* bc, int nrhs) {
+    const long long N = h->Nl[level], Nc = h->Nl[level + 1];
+    cx<T>* tmp = nullptr;
+    if (h->dim == 3)
+        HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(cx<T>) * N * nrhs, h->stream));
+    resid_restrict<T>(h, level, Vec<const cx<T>>{static_cast<const cx<T>*>(x), N, 0, nullptr},
+                      Vec<const cx<T>>{static_cast<const cx<T>*>(b), N, 0, nullptr},
+                      Vec<cx<T>>{static_cast<cx<T>*>(bc), Nc, 0, nullptr},
+                      Vec<cx<T>>{tmp, N, 0, nullptr}, nrhs);
+    if (tmp) HIPCHK(hipFreeAsync(tmp, h->stream));
+}
+}  // extern "C++"
+
+int helm_restrict_residual(helm_t* h, int level, int prec, const void* x, const void* b,
+                           void* b_coarse, int nrhs) {
+    if (!h || !x || !b || !b_coarse || nrhs < 1 || level < 0 || level >= h->levels - 1)
+        return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    try {
+        if (prec == HELM_FP64) restrict_t<double>(h, level, x, b, b_coarse, nrhs);
+        else restrict_t<float>(h, level, x, b, b_coarse, nrhs);
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+int helm_prolong_correct(helm_t* h, int level, int prec, const void* e_coarse, void* x, int nrhs) {
+    if (!h || !e_coarse || !x || nrhs < 1 || level < 0 || level >= h->levels - 1) return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    const long long N = h->Nl[level], Nc = h->Nl[level + 1];
+    try {
+        if (prec == HELM_FP64)
+            prolong<double>(h, level, Vec<const cxd>{static_cast<const cxd*>(e_coarse), Nc, 0, nullptr},
+                            Vec<cxd>{static_cast<cxd*>(x), N, 0, nullptr}, nrhs);
+        else
+            prolong<float>(h, level, Vec<const cxf>{static_cast<const cxf*>(e_coarse), Nc, 0, nullptr},
+                           Vec<cxf>{static_cast<cxf*>(x), N, 0, nullptr}, nrhs);
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+int helm_coarse_solve(helm_t* h, int prec, const void* b, void* x, int nrhs) {
+    if (!h || !b || !x || nrhs < 1) return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    const long long Nc = h->Nl.back();
+    try {
+        if (prec == HELM_FP64)
+            coarse_apply<double>(h->stream, h->d_cinv, h->nc,
+                                 Vec<const cxd>{static_cast<const cxd*>(b), Nc, 0, nullptr},
+                                 Vec<cxd>{static_cast<cxd*>(x), Nc, 0, nullptr}, nrhs);
+        else
+            coarse_apply<float>(h->stream, h->d_cinv, h->nc,
+                                Vec<const cxf>{static_cast<const cxf*>(b), Nc, 0, nullptr},
+                                Vec<cxf>{static_cast<cxf*>(x), Nc, 0, nullptr}, nrhs);
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs, void* workspace) {
+    if (!h || !b || !x || !workspace || nrhs < 1) return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    if (prec != h->prec) return HELM_EINVAL;  // workspace is laid out for the handle's mode
+    const long long N = h->Nl[0];
+    const Layout Lw = layout(h, nrhs);
+    try {
+        if (prec == HELM_FP64)
+            vcycle<double>(h, Lw, workspace, 0, Vec<const cxd>{static_cast<const cxd*>(b), N, 0, nullptr},
+                           Vec<cxd>{static_cast<cxd*>(x), N, 0, nullptr},
+                           at_ws<cxd>(workspace, Lw.mg_t[0], N), nrhs);
+        else
+            vcycle<float>(h, Lw, workspace, 0, Vec<const cxf>{static_cast<const cxf*>(b), N, 0, nullptr},
+                          Vec<cxf>{static_cast<cxf*>(x), N, 0, nullptr},
+                          at_ws<cxf>(workspace, Lw.mg_t[0], N), nrhs);
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+int helm_precondition(helm_t* h, const void* v, void* z, int nrhs, void* workspace) {
+    if (!h || !v || !z || !workspace || nrhs < 1) return HELM_EINVAL;
+    const long long N = h->Nl[0];
+    const Layout Lw = layout(h, nrhs);
+    try {
+        Vec<const cxd> vv{static_cast<const cxd*>(v), N, 0, nullptr};
+        if (h->prec == HELM_FP64) {
+            precondition<double>(h, Lw, workspace, vv, Vec<cxd>{static_cast<cxd*>(z), N, 0, nullptr},
+                                 nrhs);
+        } else {
+            precondition<float>(h, Lw, workspace, vv, at_ws<cxf>(workspace, Lw.Z, N), nrhs);
+            copy_cast<double, float>(h->stream, N, cst(at_ws<cxf>(workspace, Lw.Z, N)),
+                                     Vec<cxd>{static_cast<cxd*>(z), N, 0, nullptr}, nrhs);
+        }
+        HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,313 @@
+// Vector kernels of the outer FP64 flexible GMRES and of the preconditioner
+// boundary: Arnoldi inner products (deterministic two-stage reductions with
+// wavefront shuffles), basis updates, norms, precision casts, and the dense
+// FP64 coarsest-mesh solve.
+#include "launch.h"
+
+namespace helm {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int WAVE = 64;
+constexpr int NPT = 4;       // nodes per thread in reductions
+constexpr int GROUP = 4;     // Krylov vectors per reduction pass
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Sum `cnt` doubles per thread over the block; result valid in thread 0's
+// out[] (others unspecified).  lds holds (BS / WAVE) * cnt doubles.
+template <int CNT>
+__device__ __forceinline__ void block_sum(double (&v)[CNT], double* lds) {
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) v[c] = wave_sum(v[c]);
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < CNT; ++c) lds[wv * CNT + c] = v[c];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < CNT; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < BS / WAVE; ++w) s += lds[w * CNT + c];
+            v[c] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// ---- coarse solve ---------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BS) void k_coarse(const cxd* __restrict__ A, int nc,
+                                               Vec<const cx<T>> B, Vec<cx<T>> X, unsigned gx) {
+    const int slot = blockIdx.x / gx;
+    const int row = (blockIdx.x % gx) * (BS / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (row >= nc) return;
+    const cx<T>* b = B.at(slot);
+    const cxd* a = A + (long long)row * nc;
+    double re = 0.0, im = 0.0;
+    for (int c = lane; c < nc; c += WAVE) {
+        cxd bv = cvt<double>(b[c]);
+        cxd av = a[c];
+        re = fma(av.x, bv.x, fma(-av.y, bv.y, re));
+        im = fma(av.x, bv.y, fma(av.y, bv.x, im));
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) X.at(slot)[row] = mk((T)re, (T)im);
+}
+
+// ---- elementwise ------------------------------------------------------------
+template <typename TO, typename TI>
+__global__ __launch_bounds__(BS) void k_copy_cast(long long N, Vec<const cx<TI>> X,
+                                                  Vec<cx<TO>> Y, unsigned gx) {
+    const int slot = blockIdx.x / gx;
+    const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
+    if (t >= N) return;
+    Y.at(slot)[t] = cvt<TO>(X.at(slot)[t]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_axpy1(long long N, Vec<const cx<T>> X, Vec<cx<T>> Y,
+                                              unsigned gx) {
+    const int slot = blockIdx.x / gx;
+    const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
+    if (t >= N) return;
+    cx<T>* y = Y.at(slot);
+    y[t] = y[t] + X.at(slot)[t];
+}
+
+__global__ __launch_bounds__(BS) void k_scale_inv(long long N, Vec<const cxd> X, Vec<cxd> Y,
+                                                  const double* div, int dstride, unsigned gx) {
+    const int slot = blockIdx.x / gx;
+    const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
+    if (t >= N) return;
+    const double d = div[slot * dstride];
+    const double s = d != 0.0 ? 1.0 / d : 0.0;
+    Y.at(slot)[t] = s * X.at(slot)[t];
+}
+
+__global__ __launch_bounds__(BS) void k_real_to_complex(long long N, const double* f, cxd* b,
+                                                        unsigned gx) {
+    const int slot = blockIdx.x / gx;
+    const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
+    if (t >= N) return;
+    b[slot * N + t] = mk(f[slot * N + t], 0.0);
+}
+
+// ---- Arnoldi reductions -------------------------------------------------------
+// part[(slot * m + i) * nblk + blk] = sum over the block's nodes of conj(V_i) w
+__global__ __launch_bounds__(BS) void k_multidot(long long N, int m, Vec<const cxd> V,
+                                                 Vec<const cxd> W, cxd* part, unsigned nblk) {
+    __shared__ double lds[(BS / WAVE) * 2 * GROUP];
+    const int slot = blockIdx.x / nblk;
+    const unsigned blk = blockIdx.x % nblk;
+    const long long base = (long long)blk * BS * NPT + threadIdx.x;
+    const cxd* w = W.at(slot);
+    const cxd* v0 = V.at(slot);
+    cxd wv[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        long long t = base + (long long)q * BS;
+        wv[q] = t < N ? w[t] : mk(0.0, 0.0);
+    }
+    for (int i0 = 0; i0 < m; i0 += GROUP) {
+        double acc[2 * GROUP];
+#pragma unroll
+        for (int c = 0; c < 2 * GROUP; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int u = 0; u < GROUP; ++u) {
+            if (i0 + u < m) {
+                const cxd* v = v0 + (long long)(i0 + u) * N;
+#pragma unroll
+                for (int q = 0; q < NPT; ++q) {
+                    long long t = base + (long long)q * BS;
+                    if (t < N) {
+                        cxd p = cjmul(v[t], wv[q]);
+                        acc[2 * u] += p.x;
+                        acc[2 * u + 1] += p.y;
+                    }
+                }
+            }
+        }
+        block_sum<2 * GROUP>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int u = 0; u < GROUP; ++u)
+                if (i0 + u < m)
+                    part[((long long)slot * m + i0 + u) * nblk + blk] = mk(acc[2 * u], acc[2 * u + 1]);
+        }
+    }
+}
+
+// one block per (slot, i): out = sum over blocks, fixed order
+__global__ __launch_bounds__(BS) void k_reduce_parts(int m, int nblk, const cxd* part, cxd* out,
+                                                     int ostride, int accumulate) {
+    __shared__ double lds[(BS / WAVE) * 2];
+    const int slot = blockIdx.x / m, i = blockIdx.x % m;
+    const cxd* p = part + ((long long)slot * m + i) * nblk;
+    double acc[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += BS) {
+        acc[0] += p[b].x;
+        acc[1] += p[b].y;
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        cxd* o = out + (long long)slot * ostride + i;
+        cxd r = mk(acc[0], acc[1]);
+        *o = accumulate ? (*o + r) : r;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_norm2(long long N, Vec<const cxd> W, double* part,
+                                              unsigned nblk) {
+    __shared__ double lds[BS / WAVE];
+    const int slot = blockIdx.x / nblk;
+    const unsigned blk = blockIdx.x % nblk;
+    const long long base = (long long)blk * BS * NPT + threadIdx.x;
+    const cxd* w = W.at(slot);
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        long long t = base + (long long)q * BS;
+        if (t < N) {
+            cxd v = w[t];
+            acc[0] += v.x * v.x + v.y * v.y;
+        }
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[(long long)slot * nblk + blk] = acc[0];
+}
+
+__global__ __launch_bounds__(BS) void k_norm2_final(int nblk, const double* part, double* out,
+                                                    int ostride) {
+    __shared__ double lds[BS / WAVE];
+    const int slot = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += BS) acc[0] += part[(long long)slot * nblk + b];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) out[(long long)slot * ostride] = sqrt(acc[0]);
+}
+
+// w -= sum_i h_i V_i   (h from device memory, staged in LDS)
+__global__ __launch_bounds__(BS) void k_multi_axpy(long long N, int m, Vec<const cxd> V,
+                                                   const cxd* h, int hstride, Vec<cxd> W,
+                                                   unsigned gx) {
+    extern __shared__ cxd hs[];
+    const int slot = blockIdx.x / gx;
+    for (int i = threadIdx.x; i < m; i += BS) hs[i] = h[(long long)slot * hstride + i];
+    __syncthreads();
+    const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
+    if (t >= N) return;
+    const cxd* v = V.at(slot);
+    cxd acc = mk(0.0, 0.0);
+    for (int i = 0; i < m; ++i) acc = cfma(hs[i], v[(long long)i * N + t], acc);
+    cxd* w = W.at(slot);
+    w[t] = w[t] - acc;
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(BS) void k_update_solution(long long N, int m, Vec<const cx<TZ>> Z,
+                                                        const cxd* y, int ystride, Vec<cxd> X,
+                                                        unsigned gx) {
+    extern __shared__ cxd ys[];
+    const int slot = blockIdx.x / gx;
+    for (int i = threadIdx.x; i < m; i += BS) ys[i] = y[(long long)slot * ystride + i];
+    __syncthreads();
+    const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
+    if (t >= N) return;
+    const cx<TZ>* z = Z.at(slot);
+    cxd acc = mk(0.0, 0.0);
+    for (int i = 0; i < m; ++i) acc = cfma(ys[i], cvt<double>(z[(long long)i * N + t]), acc);
+    cxd* x = X.at(slot);
+    x[t] = x[t] + acc;
+}
+
+inline unsigned blocks(long long N) { return (unsigned)((N + BS - 1) / BS); }
+
+}  // namespace
+
+int multidot_blocks(long long N) { return (int)((N + (long long)BS * NPT - 1) / ((long long)BS * NPT)); }
+
+template <typename T>
+void coarse_apply(hipStream_t st, const cxd* Ainv, int nc, Vec<const cx<T>> B, Vec<cx<T>> X,
+                  int nslots) {
+    const unsigned gx = (nc + BS / WAVE - 1) / (BS / WAVE);
+    k_coarse<T><<<gx * nslots, BS, 0, st>>>(Ainv, nc, B, X, gx);
+}
+
+template <typename TO, typename TI>
+void copy_cast(hipStream_t st, long long N, Vec<const cx<TI>> X, Vec<cx<TO>> Y, int nslots) {
+    const unsigned gx = blocks(N);
+    k_copy_cast<TO, TI><<<gx * nslots, BS, 0, st>>>(N, X, Y, gx);
+}
+
+template <typename T>
+void axpy1(hipStream_t st, long long N, Vec<const cx<T>> X, Vec<cx<T>> Y, int nslots) {
+    const unsigned gx = blocks(N);
+    k_axpy1<T><<<gx * nslots, BS, 0, st>>>(N, X, Y, gx);
+}
+
+void scale_inv(hipStream_t st, long long N, Vec<const cxd> X, Vec<cxd> Y, const double* div,
+               int div_stride, int nslots) {
+    const unsigned gx = blocks(N);
+    k_scale_inv<<<gx * nslots, BS, 0, st>>>(N, X, Y, div, div_stride, gx);
+}
+
+void real_to_complex(hipStream_t st, long long N, const double* f, cxd* b, int nslots) {
+    const unsigned gx = blocks(N);
+    k_real_to_complex<<<gx * nslots, BS, 0, st>>>(N, f, b, gx);
+}
+
+void multidot(hipStream_t st, long long N, int m, Vec<const cxd> V, Vec<const cxd> W, cxd* part,
+              int nslots) {
+    const unsigned nblk = multidot_blocks(N);
+    k_multidot<<<nblk * nslots, BS, 0, st>>>(N, m, V, W, part, nblk);
+}
+
+void reduce_parts(hipStream_t st, int m, int nblk, const cxd* part, cxd* out, int ostride,
+                  int accumulate, int nslots) {
+    k_reduce_parts<<<m * nslots, BS, 0, st>>>(m, nblk, part, out, ostride, accumulate);
+}
+
+void multi_axpy(hipStream_t st, long long N, int m, Vec<const cxd> V, const cxd* h, int hstride,
+                Vec<cxd> W, int nslots) {
+    const unsigned gx = blocks(N);
+    k_multi_axpy<<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, V, h, hstride, W, gx);
+}
+
+void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* out, int ostride,
+           int nslots) {
+    const unsigned nblk = multidot_blocks(N);
+    k_norm2<<<nblk * nslots, BS, 0, st>>>(N, W, part, nblk);
+    k_norm2_final<<<nslots, BS, 0, st>>>(nblk, part, out, ostride);
+}
+
+template <typename TZ>
+void update_solution(hipStream_t st, long long N, int m, Vec<const cx<TZ>> Z, const cxd* y,
+                     int ystride, Vec<cxd> X, int nslots) {
+    const unsigned gx = blocks(N);
+    k_update_solution<TZ><<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, Z, y, ystride, X, gx);
+}
+
+template void coarse_apply<double>(hipStream_t, const cxd*, int, Vec<const cxd>, Vec<cxd>, int);
+template void coarse_apply<float>(hipStream_t, const cxd*, int, Vec<const cxf>, Vec<cxf>, int);
+template void copy_cast<double, double>(hipStream_t, long long, Vec<const cxd>, Vec<cxd>, int);
+template void copy_cast<float, double>(hipStream_t, long long, Vec<const cxd>, Vec<cxf>, int);
+template void copy_cast<double, float>(hipStream_t, long long, Vec<const cxf>, Vec<cxd>, int);
+template void copy_cast<float, float>(hipStream_t, long long, Vec<const cxf>, Vec<cxf>, int);
+template void axpy1<double>(hipStream_t, long long, Vec<const cxd>, Vec<cxd>, int);
+template void axpy1<float>(hipStream_t, long long, Vec<const cxf>, Vec<cxf>, int);
+template void update_solution<double>(hipStream_t, long long, int, Vec<const cxd>, const cxd*,
+                                      int, Vec<cxd>, int);
+template void update_solution<float>(hipStream_t, long long, int, Vec<const cxf>, const cxd*,
+                                     int, Vec<cxd>, int);
+
+}  // namespace helm

@@ -1,0 +1,72 @@
+// Host-side launchers of the HIP kernels (internal to libhelm).
+#pragma once
+
+#include "helm_common.h"
+
+namespace helm {
+
+// ---- 2D P1 stencils (kernels2d.hip) ---------------------------------------
+// mode: StencilMode; s: scale for MODE_RESID.  X may be null for JACOBI0,
+// B null for APPLY.
+template <typename T, typename TI>
+void stencil2d(hipStream_t st, const Op2<T>& op, int mode, T s, Vec<const cx<TI>> X,
+               Vec<const cx<T>> B, Vec<cx<T>> Y, int nslots);
+
+// b_c = P^T r  (fine level with n cells -> n/2)
+template <typename T>
+void restrict2d(hipStream_t st, int n, Vec<const cx<T>> R, Vec<cx<T>> Bc, int nslots);
+
+// b_c = P^T (b - L x), residual formed on the fly
+template <typename T>
+void resid_restrict2d(hipStream_t st, const Op2<T>& op, Vec<const cx<T>> X, Vec<const cx<T>> B,
+                      Vec<cx<T>> Bc, int nslots);
+
+// x += P e  (coarse level with n/2 cells -> fine n)
+template <typename T>
+void prolong2d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslots);
+
+// ---- 3D Q1 stencils (kernels3d.hip) ---------------------------------------
+template <typename T, typename TI>
+void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>> X,
+               Vec<const cx<T>> B, Vec<cx<T>> Y, int nslots);
+template <typename T>
+void restrict3d(hipStream_t st, int n, Vec<const cx<T>> R, Vec<cx<T>> Bc, int nslots);
+template <typename T>
+void prolong3d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslots);
+
+// ---- vector kernels (kernels_vec.hip) ----------------------------------------
+// x = Ainv b on the coarsest mesh, Ainv dense complex FP64 (nc x nc, row-major)
+template <typename T>
+void coarse_apply(hipStream_t st, const cxd* Ainv, int nc, Vec<const cx<T>> B, Vec<cx<T>> X,
+                  int nslots);
+// y = x (type conversion allowed)
+template <typename TO, typename TI>
+void copy_cast(hipStream_t st, long long N, Vec<const cx<TI>> X, Vec<cx<TO>> Y, int nslots);
+// y += x
+template <typename T>
+void axpy1(hipStream_t st, long long N, Vec<const cx<T>> X, Vec<cx<T>> Y, int nslots);
+// y = alpha x, alpha real per slot: y = x / div[slot]  (div read on device)
+void scale_inv(hipStream_t st, long long N, Vec<const cxd> X, Vec<cxd> Y, const double* div,
+               int div_stride, int nslots);
+// partial dot products: part[slot][i][blk] = sum_{n in blk} conj(V_i[n]) w[n], i < m
+// V_i at Vb.at(slot) + i*N
+int multidot_blocks(long long N);
+void multidot(hipStream_t st, long long N, int m, Vec<const cxd> V, Vec<const cxd> W, cxd* part,
+              int nslots);
+// reduce part over blocks: out[slot*ostride + i] (+)= sum_blk part[slot][i][blk]
+void reduce_parts(hipStream_t st, int m, int nblk, const cxd* part, cxd* out, int ostride,
+                  int accumulate, int nslots);
+// w -= sum_{i<m} h[slot*hstride + i] V_i
+void multi_axpy(hipStream_t st, long long N, int m, Vec<const cxd> V, const cxd* h, int hstride,
+                Vec<cxd> W, int nslots);
+// squared norm partials: part[slot][blk] = sum |w|^2 ; reduced into out[slot*ostride]
+void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* out, int ostride,
+           int nslots);
+// x += sum_{i<m} y[slot*ystride + i] Z_i  (Z in FP64 or FP32)
+template <typename TZ>
+void update_solution(hipStream_t st, long long N, int m, Vec<const cx<TZ>> Z, const cxd* y,
+                     int ystride, Vec<cxd> X, int nslots);
+// b = f (real -> complex)
+void real_to_complex(hipStream_t st, long long N, const double* f, cxd* b, int nslots);
+
+}  // namespace helm

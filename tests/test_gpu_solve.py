@@ -1,0 +1,100 @@
+"""End-to-end parity of helm_solve against the oracle.
+
+The method converges to the unique discrete solution u = B_0^{-1} b, so the
+GPU result is compared with the oracle's direct solve: relative l2 error
+<= 1e-6 for the FP64 path and <= 1e-5 for the FP32-multigrid path at the
+1e-8 residual tolerance, and the true residual is recomputed with the
+oracle's assembled CSR B_0.  Iteration counts are not unique (rounding,
+CGS2 vs MGS) and must agree with the oracle's FGMRES within +-1.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import solver as osolver
+import workloads as W
+from gpu_util import to_dev, to_host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(dim, n, levels, k, precision="fp64", **kw):
+    from paper_2506_18694_amd import Solver
+    return Solver(dim, n, levels, k, 0.0, k, precision=precision, **kw)
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = W.WORKLOADS["p1-64-k10"]
+    pr = osolver.Problem(2, w["n"], w["k"], w["delta_hat"], levels=w["levels"])
+    f = W.workload_sources("p1-64-k10")
+    b = np.stack([pr.M @ fi for fi in f])
+    u = np.stack([pr.solve_direct(bi) for bi in b])
+    _, info = pr.solve(b[0], tol=1e-8, inner="mg")
+    return w, pr, b, u, info["its"]
+
+
+@pytest.mark.parametrize("prec,tol_err", [("fp64", 1e-6), ("fp32", 1e-5)])
+def test_small_workload(small, prec, tol_err):
+    w, pr, b, u, oracle_its = small
+    s = _solver(2, w["n"], w["levels"], w["k"], prec)
+    x, st = s.solve(to_dev(b), tol=1e-8)
+    x = to_host(x)
+    assert st["status"] == 0 and st["converged"] == 1
+    assert rel_l2(x, u) < tol_err
+    r = np.linalg.norm(b[0] - pr.B0 @ x[0]) / np.linalg.norm(b[0])
+    assert r <= 1e-8 * 1.01
+    assert abs(st["outer_its"] - oracle_its) <= 1, (st["outer_its"], oracle_its)
+    assert st["hss_steps"] == 10
+
+
+@pytest.mark.parametrize("prec,tol_err", [("fp64", 1e-9), ("fp32", 1e-9)])
+def test_small_workload_tight(small, prec, tol_err):
+    w, pr, b, u, _ = small
+    s = _solver(2, w["n"], w["levels"], w["k"], prec)
+    x, st = s.solve(to_dev(b), tol=1e-12)
+    assert st["converged"] == 1
+    assert rel_l2(to_host(x), u) < tol_err
+
+
+def test_multiple_rhs_equal_single_solves():
+    n, k, levels = 64, 10.0, 3
+    pr = osolver.Problem(2, n, k, k, levels=levels)
+    centres = W.seeded_centres(4, 2, 3)
+    f = np.stack([W.gaussian_nodal(2, n, c, 0.05) for c in centres])
+    f[2] = 0.0                                 # a zero column converges at once
+    b = np.stack([pr.M @ fi for fi in f])
+    s = _solver(2, n, levels, k)
+    xb, st = s.solve(to_dev(b), tol=1e-10)
+    xb = to_host(xb)
+    assert st["converged"] == 1
+    assert np.abs(xb[2]).max() == 0.0
+    for c in (0, 1, 3):
+        x1, _ = s.solve(to_dev(b[c:c + 1]), tol=1e-10)
+        assert rel_l2(to_host(x1)[0], xb[c]) < 1e-12
+        assert rel_l2(xb[c], pr.solve_direct(b[c])) < 1e-8
+
+
+def test_3d_small_solve():
+    n, k, levels = 16, 4.0, 3
+    pr = osolver.Problem(3, n, k, k, levels=levels)
+    f = W.gaussian_nodal(3, n, (0.4, 0.55, 0.5), 0.15)
+    b = (pr.M @ f)[None]
+    u = pr.solve_direct(b[0])
+    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-5)):
+        s = _solver(3, n, levels, k, prec)
+        x, st = s.solve(to_dev(b), tol=1e-8)
+        assert st["converged"] == 1
+        assert rel_l2(to_host(x)[0], u) < tol
+
+
+def test_no_convergence_reports_enoconv():
+    n, k, levels = 64, 10.0, 3
+    pr = osolver.Problem(2, n, k, k, levels=levels)
+    b = (pr.M @ W.gaussian_nodal(2, n, (0.5, 0.5), 0.05))[None]
+    s = _solver(2, n, levels, k, max_outer=3, restart=3)
+    x, st = s.solve(to_dev(b), tol=1e-10)
+    assert st["status"] == -4 and st["converged"] == 0
+    assert st["outer_its"] == 3
+    r = np.linalg.norm(b[0] - pr.B0 @ to_host(x)[0]) / np.linalg.norm(b[0])
+    assert abs(r - st["true_rel_residual"]) < 1e-10

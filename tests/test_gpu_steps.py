@@ -1,0 +1,151 @@
+"""Parity of every step of the hot path (HIP, through the C ABI) against the
+CPU oracle, element by element, on seeded inputs at sizes spanning several
+256-node tiles with ragged tails, for 1 and several right-hand sides.
+
+Tolerances.  FP64 steps: max-norm error <= 1e-12 relative to the max-norm
+of the oracle result (summation order is the only difference).  FP32 steps:
+the oracle receives the same FP32-rounded inputs and works in FP64; one
+stencil pass loses at most a few FP32 ulps of sum |w_ij x_j|, so 2e-5
+relative is used; composite steps (V-cycle, preconditioner) accumulate
+over passes and levels and use 2e-4 relative l2.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fem, multigrid, operators as ops, solver as osolver
+import workloads as W
+from gpu_util import oracle_matrix, to_dev, to_host, rel_err, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 2e-5}
+
+
+def _solver(dim, n, levels, k, dh, precision="fp64", **kw):
+    from paper_2506_18694_amd import Solver
+    return Solver(dim, n, levels, k, 0.0, dh, precision=precision, **kw)
+
+
+def _inputs(N, nrhs, seed, prec):
+    x = W.random_complex((nrhs, N), seed)
+    if prec == "fp32":
+        x = x.astype(np.complex64).astype(np.complex128)
+    return x
+
+
+CASES_2D = [(2, 1), (5, 1), (24, 3), (33, 1), (64, 3)]
+CASES_3D = [(2, 1), (4, 2), (7, 1), (16, 2)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim,n,levels", [(2, n, l) for n, l in CASES_2D] + [(3, n, l) for n, l in CASES_3D])
+@pytest.mark.parametrize("op", ["B0", "BSHIFT", "L", "N", "H", "M"])
+def test_operator_apply(op, dim, n, levels, prec):
+    k, dh = 7.5, 7.5
+    s = _solver(dim, n, 1 if n % 2 else levels, k, dh, prec)
+    N = s.nodes(0)
+    for nrhs in (1, 3):
+        x = _inputs(N, nrhs, 11 + nrhs, prec)
+        y = to_host(s.apply(op, to_dev(x, "complex128" if prec == "fp64" else "complex64")))
+        A = oracle_matrix(dim, n, op, k, dh)
+        ref = np.stack([A @ xi for xi in x])
+        assert rel_err(y, ref) < TOL[prec], (op, dim, n, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim,n,levels", [(2, 64, 3), (2, 24, 3), (3, 8, 3), (3, 16, 2)])
+def test_transfer_and_smoother_steps(dim, n, levels, prec):
+    k, dh = 6.0, 6.0
+    dt = "complex128" if prec == "fp64" else "complex64"
+    s = _solver(dim, n, levels, k, dh, prec)
+    hier = multigrid.Hierarchy(dim, n, levels, ops.coefficients("L", k, dh))
+    for l in range(levels):
+        lev = hier.levels[l]
+        N = lev.A.shape[0]
+        x = _inputs(N, 2, 30 + l, prec)
+        b = _inputs(N, 2, 40 + l, prec)
+        # Jacobi sweep with and without an initial guess
+        y = to_host(s.jacobi(to_dev(b, dt), to_dev(x, dt), level=l))
+        ref = np.stack([multigrid.jacobi_sweep(lev, xi, bi, 2.0 / 3.0) for xi, bi in zip(x, b)])
+        assert rel_err(y, ref) < TOL[prec], ("jacobi", l)
+        y0 = to_host(s.jacobi(to_dev(b, dt), None, level=l))
+        ref0 = np.stack([multigrid.jacobi_sweep(lev, np.zeros(N), bi, 2.0 / 3.0) for bi in b])
+        assert rel_err(y0, ref0) < TOL[prec], ("jacobi0", l)
+        if l == levels - 1:
+            continue
+        # residual restriction b_c = P^T (b - L x)
+        bc = to_host(s.restrict_residual(to_dev(x, dt), to_dev(b, dt), level=l))
+        refc = np.stack([lev.P.T @ (bi - lev.A @ xi) for xi, bi in zip(x, b)])
+        assert rel_err(bc, refc) < TOL[prec], ("restrict", l)
+        # prolongation + correction x += P e
+        Nc = hier.levels[l + 1].A.shape[0]
+        e = _inputs(Nc, 2, 50 + l, prec)
+        xd = to_dev(x, dt)
+        s.prolong_correct(to_dev(e, dt), xd, level=l)
+        refp = np.stack([xi + lev.P @ ei for xi, ei in zip(x, e)])
+        assert rel_err(to_host(xd), refp) < TOL[prec], ("prolong", l)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim,n,levels", [(2, 64, 3), (2, 32, 2), (3, 8, 2)])
+def test_coarse_solve(dim, n, levels, prec):
+    k = 10.0
+    dt = "complex128" if prec == "fp64" else "complex64"
+    s = _solver(dim, n, levels, k, k, prec)
+    nc = n >> (levels - 1)
+    A = oracle_matrix(dim, nc, "L", k, k).toarray()
+    b = _inputs(A.shape[0], 3, 7, prec)
+    x = to_host(s.coarse_solve(to_dev(b, dt)))
+    ref = np.linalg.solve(A, b.T).T
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    assert rel_err(x, ref) < tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_hss_residual(prec):
+    k, dh, n = 12.0, 12.0, 40
+    dt = "complex128" if prec == "fp64" else "complex64"
+    s = _solver(2, n, 1, k, dh, prec)
+    N = s.nodes(0)
+    R = _inputs(N, 2, 3, prec)
+    u = _inputs(N, 2, 4, prec)
+    B = oracle_matrix(2, n, "BSHIFT", k, dh)
+    c = 2 * k / (k + 1)
+    rho = to_host(s.hss_residual(to_dev(R, dt), to_dev(u, dt)))
+    ref = np.stack([c * (Ri - B @ ui) for Ri, ui in zip(R, u)])
+    assert rel_err(rho, ref) < TOL[prec]
+    rho0 = to_host(s.hss_residual(to_dev(R, dt), None))
+    assert rel_err(rho0, c * R) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-4)])
+@pytest.mark.parametrize("dim,n,levels,k", [(2, 64, 3, 10.0), (2, 96, 4, 15.0), (3, 16, 3, 4.0)])
+def test_vcycle_matches_oracle(dim, n, levels, k, prec, tol):
+    dt = "complex128" if prec == "fp64" else "complex64"
+    s = _solver(dim, n, levels, k, k, prec, restart=4)
+    pr = osolver.Problem(dim, n, k, k, levels=levels)
+    b = _inputs(s.nodes(0), 2, 21, prec)
+    x = to_host(s.vcycle(to_dev(b, dt)))
+    ref = np.stack([pr.vcycle(bi) for bi in b])
+    assert rel_l2(x, ref) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 5e-4)])
+@pytest.mark.parametrize("dim,n,levels,k", [(2, 64, 3, 10.0), (2, 48, 2, 7.3), (3, 8, 2, 3.0)])
+def test_preconditioner_matches_oracle(dim, n, levels, k, prec, tol):
+    s = _solver(dim, n, levels, k, k, prec, restart=4)
+    pr = osolver.Problem(dim, n, k, k, levels=levels)
+    v = W.random_complex((3, s.nodes(0)), 5)
+    z = to_host(s.precondition(to_dev(v)))
+    ref = np.stack([pr.precond(vi, inner="mg") for vi in v])
+    assert rel_l2(z, ref) < tol
+
+
+def test_load_nodal_is_mass_times_source():
+    import torch
+    s = _solver(2, 64, 3, 10.0, 10.0)
+    f = W.workload_sources("p1-64-k10")
+    b = to_host(s.load_nodal(torch.from_numpy(f).cuda()))
+    K, M, MG = fem.assemble_2d(64)
+    assert rel_err(b, np.stack([M @ fi for fi in f])) < 1e-13
