@@ -1,0 +1,182 @@
+"""Throughput benchmark: solved degrees of freedom per second to a 1e-8
+relative residual for the shifted-HSS Helmholtz solver on one MI355X.
+
+One step = one complete helm_solve (outer FP64 FGMRES, shifted-HSS
+preconditioner with ceil(k) HSS sweeps, one V(2,2) cycle per sweep, all
+right-hand sides) with the load vectors already resident in HBM.
+
+Default workload: 2D P1, 1024 x 1024 right-diagonal mesh (N = 1,050,625
+nodes), k = 100, delta = 0, delta_hat = k, 8 multigrid levels, four
+Gaussian sources (sigma 0.02) at seeded uniform centres, plain complex
+FP64 on the GPU.  The same workload is also solved with FP32 multigrid and
+FP64 outer iteration, reported as `fp32_mg`.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solved DOFs/s to 1e-8 rel residual (FP32-MG vs FP64), %HBM peak; p50/p99 latency"
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels2d.hip", "helm_common.h", "stencil_rows.h"):
+        with open(os.path.join(ROOT, "paper_2506_18694_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, precision):
+    """HBM traffic per launch of the dominant kernel from committed rocprofv3
+    counter runs; null when the kernel source changed since they were taken."""
+    path = os.path.join(PROFILES, "traffic_jacobi_%s_%s.json" % (workload, precision))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_solves(W, name, precision, steps, warmup, tol):
+    import torch
+    from paper_2506_18694_amd import Solver
+    w = W.WORKLOADS[name]
+    s = Solver(w["dim"], w["n"], w["levels"], w["k"], w["delta"], w["delta_hat"],
+               precision=precision, profile=True)
+    f = torch.from_numpy(W.workload_sources(name)).cuda().contiguous()
+    b = s.load_nodal(f)
+    x = torch.empty_like(b)
+    ws = s.workspace(b.shape[0])
+    log("[bench] %s %s: N=%d nrhs=%d workspace %.1f GB" % (name, precision, s.N, b.shape[0],
+                                                           ws.numel() / 1e9))
+    for i in range(warmup):
+        _, st = s.solve(b, x, tol=tol, workspace=ws)
+        log("[bench] warmup %d: %.1f ms, outer its %d, true rel res %.2e"
+            % (i, st["solve_ms"], st["outer_its"], st["true_rel_residual"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(steps):
+        _, st = s.solve(b, x, tol=tol, workspace=ws)
+        stats.append(st)
+        log("[bench] step %d: %.1f ms, outer its %d, true rel res %.2e"
+            % (i, st["solve_ms"], st["outer_its"], st["true_rel_residual"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ok = all(st["converged"] == 1 and st["true_rel_residual"] <= tol for st in stats)
+    s.close()
+    return dict(N=s.N, nrhs=b.shape[0], elapsed=elapsed, stats=stats, ok=ok, w=w)
+
+
+def cpu_baseline(W, name, outer_its, sample_steps):
+    """The oracle's HSS sweep (one CSR V-cycle per step, correction form) timed
+    on the host for one right-hand side, extrapolated to a full solve with the
+    GPU's outer iteration count."""
+    import numpy as np
+    from oracle import solver as osolver, hss
+    w = W.WORKLOADS[name]
+    pr = osolver.Problem(w["dim"], w["n"], w["k"], w["delta_hat"], levels=w["levels"])
+    f = W.workload_sources(name)[0]
+    R = pr.M @ f
+    _ = pr.hierarchy
+    t0 = time.perf_counter()
+    hss.hss_correction(pr.Bdh, R, w["k"], sample_steps, pr.vcycle)
+    t_step = (time.perf_counter() - t0) / sample_steps
+    nrhs = w["nrhs"]
+    t_solve = nrhs * outer_its * pr.hss_steps() * t_step
+    N = (w["n"] + 1) ** w["dim"]
+    return {"value": N * nrhs / t_solve, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": "%d HSS steps (CSR V(2,2) each) for 1 of %d right-hand sides on the %s mesh, "
+                      "%.3f s per step, extrapolated to %d outer its x %d steps x %d rhs"
+                      % (sample_steps, nrhs, name, t_step, outer_its, pr.hss_steps(), nrhs)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="p1-1024-k100")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X and "
+              "this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    name = args.workload
+    prec = W.WORKLOADS[name]["precision"]
+    main_prec = "fp64" if prec == "fp64" else "fp32"
+    r = run_solves(W, name, main_prec, args.steps, args.warmup, args.tol)
+    ms = r["elapsed"] / args.steps * 1e3
+    value = r["N"] * r["nrhs"] / (ms / 1e3)
+    sw_ms = sum(st["sweep_ms"] for st in r["stats"])
+    sw_n = sum(st["sweep_launches"] for st in r["stats"])
+    sw_b = sum(st["sweep_bytes"] for st in r["stats"])
+    achieved = sw_b / (sw_ms / 1e3) / 1e9 if sw_ms > 0 else None
+    per_launch = sw_b / sw_n if sw_n else None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": stored_traffic(name, main_prec),
+            "kernel": "finest-level Jacobi sweep (k_stencil2d, MODE_JACOBI)",
+            "bytes_per_launch": per_launch,
+            "avg_launch_us": sw_ms / sw_n * 1e3 if sw_n else None}
+    w = r["w"]
+    out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if main_prec == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": name, "dim": w["dim"], "n": w["n"], "dofs": r["N"],
+                      "nrhs": r["nrhs"], "k": w["k"], "delta_hat": w["delta_hat"],
+                      "levels": w["levels"], "precision": main_prec, "tol": args.tol,
+                      "outer_its": max(st["outer_its"] for st in r["stats"]),
+                      "hss_steps": r["stats"][0]["hss_steps"],
+                      "true_rel_residual": max(st["true_rel_residual"] for st in r["stats"]),
+                      "converged": r["ok"]},
+           "roofline": roof}
+    if not args.no_fp32 and main_prec == "fp64":
+        r32 = run_solves(W, name, "fp32", 1, 1, args.tol)
+        ms32 = r32["elapsed"] * 1e3
+        v32 = r32["N"] * r32["nrhs"] / (ms32 / 1e3)
+        s32 = r32["stats"][0]
+        out["fp32_mg"] = {"value": v32, "ms_per_step": ms32, "ratio_vs_fp64": v32 / value,
+                          "outer_its": s32["outer_its"],
+                          "true_rel_residual": s32["true_rel_residual"],
+                          "sweep_GBs": s32["sweep_bytes"] / (s32["sweep_ms"] / 1e3) / 1e9
+                          if s32["sweep_ms"] > 0 else None,
+                          "converged": r32["ok"]}
+    if not args.no_cpu_baseline:
+        log("[bench] oracle CPU baseline sample ...")
+        out["cpu_baseline"] = cpu_baseline(W, name, out["config"]["outer_its"],
+                                           args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

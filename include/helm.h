@@ -102,6 +102,24 @@ typedef struct {
     int    restart;    /* FGMRES basis size; 0 = 3*ceil(k) + 30, max 2000    */
     int    max_outer;  /* outer iteration cap; 0 = 4 * restart               */
     int    x0_given;   /* 1: x holds the initial guess on entry, else x0 = 0 */
+    int    profile;    /* 1: time every finest-level Jacobi sweep of the
+                          solve with HIP events (fills the sweep_* stats)    */
+    int    mg_cycles;  /* V-cycles per inner HSS solve (each after the first
+                          starts from the previous iterate).  0 = automatic:
+                          with exact inner solves the HSS error contracts by
+                          (k-1)/(k+1) per step (Sec. 3.1 proposition); an
+                          inexact solve keeps that only while its error is
+                          below the gap 2/(k+1), so the library measures the
+                          V-cycle rate rho_V once (power iteration) and uses
+                          the smallest q >= 2 with rho_V^q <= 2/(k+1).       */
+    int    no_graphs;  /* 1: launch the preconditioner's kernels one by one;
+                          default 0 replays one captured HIP graph of the
+                          whole HSS loop per application (captured on a
+                          private stream, launched on the handle's stream)  */
+    int    no_small;   /* 1: run every 2D level with per-level kernels; by
+                          default the levels from the first one whose
+                          vectors fit one workgroup's LDS down to the
+                          coarsest run as one LDS-resident kernel per cycle  */
 } helm_opts;
 
 typedef struct {
@@ -115,6 +133,15 @@ typedef struct {
                                     recomputed in FP64 after convergence     */
     double solve_ms;             /* wall time of helm_solve                  */
     double precond_ms;           /* device time inside the preconditioner    */
+    double sweep_ms;             /* profile=1: summed device time of the
+                                    finest-level Jacobi sweep launches        */
+    long long sweep_launches;    /* profile=1: number of those launches       */
+    double sweep_bytes;          /* profile=1: algorithmic bytes they move:
+                                    read x, read b, write x' = 3 vectors per
+                                    right-hand side per launch                */
+    int    mg_cycles;            /* V-cycles per inner HSS solve used          */
+    double vcycle_rate;          /* measured V-cycle contraction (automatic
+                                    mode; 0 when mg_cycles was given)         */
 } helm_stats;
 
 /* Fill *opts with the defaults listed above. */

@@ -71,6 +71,17 @@ def vcycle(hier, b, l=0, nu1=2, nu2=2, omega=2.0 / 3.0):
     return x
 
 
+def cycles(hier, b, count, nu1=2, nu2=2, omega=2.0 / 3.0):
+    """`count` V-cycles used as a stationary iteration from x = 0:
+    x <- x + V(b - A x).  This is how "one or more multigrid cycles"
+    approximate an inner solve (Sec. 1, Sec. 5.3)."""
+    A = hier.levels[0].A
+    x = np.zeros_like(b, dtype=np.complex128)
+    for _ in range(count):
+        x = x + vcycle(hier, b - A @ x, 0, nu1, nu2, omega)
+    return x
+
+
 def error_propagator(hier, l=0, nu1=2, nu2=2, omega=2.0 / 3.0):
     """Dense error-propagation matrix of the cycle on level l, built by
     composition of its factors (used only on tiny meshes by the tests):

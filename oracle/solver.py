@@ -1,6 +1,8 @@
 """End-to-end reference solve: outer FGMRES on B_0 preconditioned by the
 shifted-HSS preconditioner (Sec. 4), whose inner solves with L are either
-exact (sparse LU, Sec. 5.2) or one V-cycle each (Sec. 5.3).
+exact (sparse LU, Sec. 5.2) or a fixed number of V-cycles each (Sec. 5.3;
+default two: with one V(2,2)-Jacobi cycle the inexact HSS iteration has
+error modes that grow, see the tests).
 
 `Problem` assembles everything once for a mesh and parameter set; the
 methods return plain numpy arrays.  The direct solution B_0^{-1} b is the
@@ -16,10 +18,11 @@ from . import fem, operators as ops, hss, multigrid, krylov
 
 class Problem:
     def __init__(self, dim, n, k, delta_hat, delta=0.0, levels=1, faces=None,
-                 nu1=2, nu2=2, omega=2.0 / 3.0, m=1):
+                 nu1=2, nu2=2, omega=2.0 / 3.0, m=1, cycles=2):
         self.dim, self.n, self.k = dim, n, float(k)
         self.delta, self.delta_hat = float(delta), float(delta_hat)
         self.nu1, self.nu2, self.omega, self.m = nu1, nu2, omega, m
+        self.cycles = cycles            # V-cycles per inner HSS solve
         self.K, self.M, self.MG = fem.assemble(dim, n, faces)
         K, M, MG = self.K, self.M, self.MG
         self.B0 = ops.b_delta(K, M, MG, k, delta).tocsr()
@@ -57,13 +60,18 @@ class Problem:
         return multigrid.vcycle(self.hierarchy, np.asarray(b, dtype=np.complex128),
                                 0, self.nu1, self.nu2, self.omega)
 
+    def mg_solve(self, b):
+        """Inner HSS solve by `cycles` V-cycles (x <- x + V(b - L x), x0 = 0)."""
+        return multigrid.cycles(self.hierarchy, np.asarray(b, dtype=np.complex128),
+                                self.cycles, self.nu1, self.nu2, self.omega)
+
     # -- preconditioner -------------------------------------------------------
     def hss_steps(self):
         return ops.inner_iterations(self.k, self.m)
 
     def precond(self, R, inner="mg", steps=None):
         """B~^{-1} R: shifted-HSS preconditioner in correction form."""
-        solve = self.vcycle if inner == "mg" else self.solve_L
+        solve = self.mg_solve if inner == "mg" else self.solve_L
         nsteps = self.hss_steps() if steps is None else steps
         return hss.hss_correction(self.Bdh, np.asarray(R, dtype=np.complex128),
                                   self.k, nsteps, solve)

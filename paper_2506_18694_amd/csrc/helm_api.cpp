@@ -181,8 +181,48 @@ struct helm_s {
     int nc = 0;             // coarsest-mesh node count
     int prec = HELM_FP64;
     double omega = 2.0 / 3.0;
+    int cycles = 2;           // V-cycles per inner HSS solve
+    bool cycles_auto = true;  // choose `cycles` from the measured cycle rate
+    double vrate = 0.0;       // measured V-cycle contraction (0 = not yet)
+
+    // captured HIP graphs of the preconditioner's HSS loop, per workspace,
+    // slot count, precision and cycle count; captured on cap_stream
+    struct GraphEntry {
+        void* ws;
+        int ns, tag, cycles;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
+
+    // optional HIP-event timing of the finest-level Jacobi sweeps
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
+    double prof_ms = 0.0, prof_bytes = 0.0, prof_pending_bytes = 0.0;
+    long long prof_launches = 0;
 
     Coef coef(int op) const { return op_coef(op, k, delta, dh); }
+
+    void prof_mark() {
+        if (prof_used == prof_ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            prof_ev.push_back(e);
+        }
+        (void)hipEventRecord(prof_ev[prof_used++], stream);
+    }
+    // called after the stream has been synchronised
+    void prof_collect() {
+        for (size_t q = 0; q + 1 < prof_used; q += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, prof_ev[q], prof_ev[q + 1]) == hipSuccess) prof_ms += ms;
+            ++prof_launches;
+        }
+        prof_bytes += prof_pending_bytes;
+        prof_pending_bytes = 0.0;
+        prof_used = 0;
+    }
 };
 
 namespace {
@@ -271,19 +311,30 @@ void prolong(helm_t* h, int l, Vec<const cx<T>> E, Vec<cx<T>> X, int ns) {
     else prolong3d<T>(h->stream, h->nl[l], E, X, ns);
 }
 
-// One V(2,2) cycle on level l for L x = b with zero initial guess; the
-// result is left in x.  Level buffers b, x, t of levels > l come from ws.
+// One V(2,2) cycle on level l for L x = b, starting from x = 0 or (guess)
+// from the x passed in; the result is left in x.  Level buffers b, x, t of
+// levels > l come from ws.  Starting from x0 gives x0 + V(b - L x0).
 template <typename T>
 void vcycle(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cx<T>> b, Vec<cx<T>> x,
-            Vec<cx<T>> t, int ns) {
+            Vec<cx<T>> t, int ns, bool guess = false) {
     if (l == h->levels - 1) {
         coarse_apply<T>(h->stream, h->d_cinv, h->nc, b, x, ns);
         return;
     }
     const T one = (T)1;
-    // pre-smoothing: t = omega D^{-1} b, x = t + omega D^{-1} (b - L t)
-    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI0, one, Vec<const cx<T>>{}, b, t, ns);
-    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, cst(t), b, x, ns);
+    const bool prof = h->prof_on && l == 0;
+    auto sweep = [&](Vec<const cx<T>> xin, Vec<cx<T>> xout) {
+        if (prof) h->prof_mark();
+        apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, xin, b, xout, ns);
+        if (prof) {
+            h->prof_mark();
+            h->prof_pending_bytes += 3.0 * sizeof(cx<T>) * (double)h->Nl[0] * ns;
+        }
+    };
+    // pre-smoothing: t = omega D^{-1} b (or t = J(x)), x = t + omega D^{-1} (b - L t)
+    if (guess) sweep(cst(x), t);
+    else apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI0, one, Vec<const cx<T>>{}, b, t, ns);
+    sweep(cst(t), x);
     const long long Nc = h->Nl[l + 1];
     Vec<cx<T>> bc = at_ws<cx<T>>(ws, Lw.mg_b[l + 1], Nc);
     Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
@@ -292,8 +343,8 @@ void vcycle(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cx<T>> b, Ve
     vcycle<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
     prolong<T>(h, l, cst(xc), x, ns);
     // post-smoothing: t = J(x), x = J(t)
-    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, cst(x), b, t, ns);
-    apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, cst(t), b, x, ns);
+    sweep(cst(x), t);
+    sweep(cst(t), x);
 }
 
 template <typename T>
@@ -308,9 +359,136 @@ void zero(hipStream_t st, cx<T>* p, long long n) {
     k_zero<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n);
 }
 
+// First level handled by the LDS-resident small-level cycle (-1: none).  The
+// levels from there down to the coarsest must fit one workgroup's LDS
+// (64 KB: b and x per level plus one shared scratch vector) and the
+// coarsest mesh must be small enough for one workgroup to apply its dense
+// inverse (at most 289 nodes).
+template <typename T>
+int small_start(const helm_t* h) {
+    if (h->dim != 2 || h->levels < 2 || h->nc > 289 || h->opts.no_small) return -1;
+    for (int l = 1; l < h->levels - 1; ++l) {
+        size_t elems = (size_t)h->Nl[l];  // shared scratch, sized for level l
+        for (int m = l; m < h->levels; ++m) elems += 2 * (size_t)h->Nl[m];
+        if (elems * sizeof(cx<T>) <= 65536 && h->levels - l <= MAX_SMALL) return l;
+    }
+    return -1;
+}
+
+template <typename T>
+void run_small(helm_t* h, int l0, Vec<const cx<T>> b, Vec<cx<T>> x, int ns) {
+    SmallCycle<T> sc{};
+    sc.nlev = h->levels - l0;
+    int off = 0;
+    for (int m = 0; m < sc.nlev; ++m) {
+        const int lev = l0 + m;
+        sc.n[m] = h->nl[lev];
+        sc.op[m] = make_op2<T>(h->coef(HELM_OP_L), h->nl[lev], h->omega);
+        sc.off_b[m] = off;
+        off += (int)h->Nl[lev];
+        sc.off_x[m] = off;
+        off += (int)h->Nl[lev];
+    }
+    for (int m = 0; m < sc.nlev; ++m) sc.off_t[m] = off;
+    off += (int)h->Nl[l0];
+    vcycle_small<T>(h->stream, sc, sizeof(cx<T>) * (size_t)off, h->d_cinv, h->nc, b, x, ns);
+}
+
+// Fused 2D cycle from a zero initial guess on level l (l >= 1 inside the HSS
+// loop, or l = 0 for a stand-alone cycle).  b is read, x and t are this
+// level's work buffers; returns the buffer holding the result (x or t).
+// Per level: one kernel for the zero-guess pre-smoothing and the residual
+// restriction, the coarser levels, one kernel for prolongation and the
+// post-smoothing; the small levels run as one LDS-resident kernel.
+template <typename T>
+Vec<cx<T>> vcycle2d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cx<T>> b,
+                         Vec<cx<T>> x, Vec<cx<T>> t, int ns) {
+    if (l == h->levels - 1) {
+        coarse_apply<T>(h->stream, h->d_cinv, h->nc, b, x, ns);
+        return x;
+    }
+    if (l == small_start<T>(h)) {
+        run_small<T>(h, l, b, x, ns);
+        return x;
+    }
+    const Op2<T> L = make_op2<T>(h->coef(HELM_OP_L), h->nl[l], h->omega);
+    const long long Nc = h->Nl[l + 1];
+    Vec<cx<T>> bc = at_ws<cx<T>>(ws, Lw.mg_b[l + 1], Nc);
+    Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
+    Vec<cx<T>> tc = at_ws<cx<T>>(ws, Lw.mg_t[l + 1], Nc);
+    pre0r_2d<T>(h->stream, L, b, x, bc, ns);
+    Vec<cx<T>> ec = vcycle2d_zero<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
+    sweeps_2d<T>(h->stream, L, 2, cst(x), cst(ec), b, t, false, ns);
+    return t;
+}
+
+// Shifted-HSS loop with fused 2D kernels: per HSS step the residual
+// rho = c (R - B u) is formed together with the first cycle's
+// pre-smoothing and residual restriction; cycle q's post-smoothing and
+// cycle q+1's pre-smoothing run as one four-sweep pass; the last
+// post-smoothing adds its result into u.
+template <typename T>
+void hss_loop2d(helm_t* h, const Layout& Lw, void* ws, int ns) {
+    const long long N = h->Nl[0];
+    Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, N);
+    Vec<cx<T>> u = at_ws<cx<T>>(ws, Lw.u, N);
+    Vec<cx<T>> rho = at_ws<cx<T>>(ws, Lw.mg_b[0], N);
+    Vec<cx<T>> xa = at_ws<cx<T>>(ws, Lw.mg_x[0], N);
+    Vec<cx<T>> xb = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
+    const T c = (T)(2.0 * h->k / (h->k + 1.0));
+    const Op2<T> L = make_op2<T>(h->coef(HELM_OP_L), h->nl[0], h->omega);
+    const Op2<T> Bs = make_op2<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega);
+    zero<T>(h->stream, u.base, N * ns);
+    if (h->levels == 1) {
+        // single level: every cycle is the exact coarse solve
+        for (int s = 0; s < h->hss_steps; ++s) {
+            Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
+            hss_pre0_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, xa, ns);
+            coarse_apply<T>(h->stream, h->d_cinv, h->nc, cst(rho), xb, ns);
+            axpy1<T>(h->stream, N, (T)1, cst(xb), u, ns);
+        }
+        return;
+    }
+    const long long N1 = h->Nl[1];
+    Vec<cx<T>> b1 = at_ws<cx<T>>(ws, Lw.mg_b[1], N1);
+    Vec<cx<T>> x1 = at_ws<cx<T>>(ws, Lw.mg_x[1], N1);
+    Vec<cx<T>> t1 = at_ws<cx<T>>(ws, Lw.mg_t[1], N1);
+    for (int s = 0; s < h->hss_steps; ++s) {
+        Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
+        hss_pre0r_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, xa, b1, ns);
+        Vec<cx<T>> x = xa, t = xb;
+        for (int q = 0; q < h->cycles; ++q) {
+            if (q > 0) resid_restrict2d<T>(h->stream, L, cst(x), cst(rho), b1, ns);
+            Vec<const cx<T>> ec = cst(vcycle2d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
+            const bool last = q == h->cycles - 1;
+            // the profiled kernel is the four-sweep pass (the single
+            // two-sweep update pass when only one cycle is used)
+            const bool prof = h->prof_on && (h->cycles == 1 || !last);
+            if (prof) h->prof_mark();
+            if (last) {
+                sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, true, ns);
+            } else {
+                sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, false, ns);
+                std::swap(x, t);
+            }
+            if (prof) {
+                h->prof_mark();
+                // algorithmic bytes: x and b read, e_c read (a quarter of a
+                // vector), x' written; u read and written instead of x' when
+                // it is the update pass
+                h->prof_pending_bytes += sizeof(cx<T>) * (double)N * ns * (last ? 4.25 : 3.25);
+            }
+        }
+    }
+}
+
 // Shifted-HSS preconditioner on the slot-major buffers R -> u (precision T).
 template <typename T>
 void hss_loop(helm_t* h, const Layout& Lw, void* ws, int ns) {
+    if (h->dim == 2) {
+        hss_loop2d<T>(h, Lw, ws, ns);
+        return;
+    }
     const long long N = h->Nl[0];
     Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, N);
     Vec<cx<T>> u = at_ws<cx<T>>(ws, Lw.u, N);
@@ -322,8 +500,63 @@ void hss_loop(helm_t* h, const Layout& Lw, void* ws, int ns) {
     for (int s = 0; s < h->hss_steps; ++s) {
         apply_mode<T>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c, cst(u), cst(R), rho, ns);
         vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns);
-        axpy1<T>(h->stream, N, cst(e), u, ns);
+        for (int q = 1; q < h->cycles; ++q) vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
+        axpy1<T>(h->stream, N, (T)1, cst(e), u, ns);
     }
+}
+
+// Number of V-cycles per inner HSS solve.  With exact inner solves the HSS
+// error contracts by nu = (k-1)/(k+1) per step in the H-norm (the Cayley
+// transform is H-unitary).  An inexact inner solve with cycle error E turns
+// the step's error map T into T + E(I - T); its contraction survives only if
+// the cycle error stays below the gap 1 - nu = 2/(k+1).  The V-cycle rate
+// rho_V is measured once per handle by power iteration on the cycle's error
+// map e <- e - V(L e) from a fixed pseudo-random start, and the smallest q
+// with rho_V^q <= 2/(k+1) is used (at least 2, at most 8).
+template <typename T>
+void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
+    if (!h->cycles_auto || h->vrate > 0.0) return;
+    const long long N = h->Nl[0];
+    Vec<cx<T>> e = at_ws<cx<T>>(ws, Lw.R, N);
+    Vec<cx<T>> r = at_ws<cx<T>>(ws, Lw.u, N);
+    Vec<cx<T>> d = at_ws<cx<T>>(ws, Lw.mg_x[0], N);
+    Vec<cx<T>> t = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
+    Vec<cxd> e64 = at_ws<cxd>(ws, Lw.V, N);
+    double* d_norm = reinterpret_cast<double*>(static_cast<char*>(ws) + Lw.dnorm);
+    double* d_npart = reinterpret_cast<double*>(static_cast<char*>(ws) + Lw.npart);
+    std::vector<cx<T>> init(N);
+    uint64_t state = 0x9E3779B97F4A7C15ull;
+    for (long long q = 0; q < N; ++q) {  // xorshift64*, uniform in [-1, 1)
+        auto next = [&]() {
+            state ^= state >> 12;
+            state ^= state << 25;
+            state ^= state >> 27;
+            return (double)((state * 0x2545F4914F6CDD1Dull) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        };
+        const double re = next(), im = next();
+        init[q] = mk((T)re, (T)im);
+    }
+    HIPCHK(hipMemcpyAsync(e.base, init.data(), sizeof(cx<T>) * N, hipMemcpyHostToDevice, h->stream));
+    const int iters = 8;
+    std::vector<double> norms;
+    for (int it = 0; it < iters; ++it) {
+        apply_mode<T>(h, HELM_OP_L, 0, MODE_APPLY, (T)1, cst(e), Vec<const cx<T>>{}, r, 1);
+        vcycle<T>(h, Lw, ws, 0, cst(r), d, t, 1);
+        axpy1<T>(h->stream, N, (T)-1, cst(d), e, 1);
+        copy_cast<double, T>(h->stream, N, cst(e), e64, 1);
+        norm2(h->stream, N, cst(e64), d_npart, d_norm, 1, 1);
+        double nv = 0.0;
+        HIPCHK(hipMemcpyAsync(&nv, d_norm, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        norms.push_back(nv);
+    }
+    double rate = std::pow(norms[iters - 1] / norms[iters - 4], 1.0 / 3.0);
+    if (!(rate > 0.0) || !std::isfinite(rate)) rate = 0.5;
+    h->vrate = rate;
+    const double gap = 2.0 / (h->k + 1.0);
+    int q = 2;
+    while (q < 8 && std::pow(rate, q) > gap) ++q;
+    h->cycles = q;
 }
 
 // z = B~^{-1} v for ns slots: v and z addressed through Vec descriptors
@@ -332,8 +565,55 @@ template <typename T>
 void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<cx<T>> z, int ns) {
     const long long N = h->Nl[0];
     copy_cast<T, double>(h->stream, N, v, at_ws<cx<T>>(ws, Lw.R, N), ns);
-    hss_loop<T>(h, Lw, ws, ns);
+    if (h->prof_on || h->opts.no_graphs) {
+        hss_loop<T>(h, Lw, ws, ns);
+    } else {
+        // the whole HSS loop (all steps, cycles and levels) replayed as one
+        // captured HIP graph; it reads R and writes u at fixed workspace
+        // addresses, so one graph serves every outer iteration
+        const int tag = (int)sizeof(T);
+        hipGraphExec_t ex = nullptr;
+        for (const auto& g : h->graphs)
+            if (g.ws == ws && g.ns == ns && g.tag == tag && g.cycles == h->cycles) ex = g.exec;
+        if (!ex) {
+            hipStream_t user = h->stream;
+            h->stream = h->cap_stream;
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            try {
+                hss_loop<T>(h, Lw, ws, ns);
+            } catch (...) {
+                (void)hipStreamEndCapture(h->stream, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                h->stream = user;
+                throw;
+            }
+            hipError_t e = hipStreamEndCapture(h->stream, &graph);
+            h->stream = user;
+            HIPCHK(e);
+            e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(e);
+            h->graphs.push_back(helm_s::GraphEntry{ws, ns, tag, h->cycles, ex});
+        }
+        HIPCHK(hipGraphLaunch(ex, h->stream));
+    }
     copy_cast<T, T>(h->stream, N, cst(at_ws<cx<T>>(ws, Lw.u, N)), z, ns);
+}
+
+// One stand-alone cycle b -> x (zero initial guess) on level 0.
+template <typename T>
+void vcycle_entry(helm_t* h, const Layout& Lw, void* ws, const void* b, void* x, int ns) {
+    const long long N = h->Nl[0];
+    Vec<const cx<T>> bv{static_cast<const cx<T>*>(b), N, 0, nullptr};
+    Vec<cx<T>> xv{static_cast<cx<T>*>(x), N, 0, nullptr};
+    Vec<cx<T>> tv = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
+    if (h->dim == 2) {
+        Vec<cx<T>> r = vcycle2d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns);
+        if (r.base != xv.base) copy_cast<T, T>(h->stream, N, cst(r), xv, ns);
+    } else {
+        vcycle<T>(h, Lw, ws, 0, bv, xv, tv, ns);
+    }
 }
 
 // ----------------------------------------------------------------- FGMRES --
@@ -407,6 +687,11 @@ int fgmres(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws, he
     }
     if (!h->opts.x0_given) zero<double>(s, x, N * nrhs);
 
+    ensure_cycles<T>(h, Lw, ws);
+    h->prof_on = h->opts.profile != 0;
+    h->prof_used = 0;
+    h->prof_ms = h->prof_bytes = h->prof_pending_bytes = 0.0;
+    h->prof_launches = 0;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -512,6 +797,7 @@ int fgmres(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws, he
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             precond_ms += ms;
+            if (h->prof_on) h->prof_collect();
             ++total_its;
             m_done = j + 1;
             std::vector<int> conv, keep;
@@ -609,7 +895,13 @@ int fgmres(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws, he
         st->true_rel_residual = worst;
         st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         st->precond_ms = precond_ms;
+        st->sweep_ms = h->prof_ms;
+        st->sweep_launches = h->prof_launches;
+        st->sweep_bytes = h->prof_bytes;
+        st->mg_cycles = h->cycles;
+        st->vcycle_rate = h->vrate;
     }
+    h->prof_on = false;
     (void)total_its;
     return ok ? HELM_OK : HELM_ENOCONV;
 }
@@ -632,6 +924,10 @@ void helm_opts_default(helm_opts* o) {
     o->restart = 0;
     o->max_outer = 0;
     o->x0_given = 0;
+    o->profile = 0;
+    o->mg_cycles = 0;
+    o->no_graphs = 0;
+    o->no_small = 0;
 }
 
 const char* helm_strerror(int status) {
@@ -664,7 +960,7 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
     if (!(k > 0.0) || !std::isfinite(k)) return HELM_EINVAL;
     if (!(delta >= 0.0) || !std::isfinite(delta)) return HELM_EINVAL;
     if (!(delta_hat > delta) || !std::isfinite(delta_hat)) return HELM_EINVAL;
-    if (o.hss_m < 1 || o.hss_steps < 0) return HELM_EINVAL;
+    if (o.hss_m < 1 || o.hss_steps < 0 || o.mg_cycles < 0 || o.mg_cycles > 16) return HELM_EINVAL;
     if (!(o.omega > 0.0 && o.omega < 2.0)) return HELM_EINVAL;
     if (o.precision != HELM_FP64 && o.precision != HELM_FP32_MG) return HELM_EINVAL;
     if (o.restart < 0 || o.max_outer < 0 || o.restart > 2000) return HELM_EINVAL;
@@ -691,6 +987,8 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
         h->stream = static_cast<hipStream_t>(hip_stream);
         HIPCHK(hipGetDevice(&h->device));
         h->hss_steps = o.hss_steps > 0 ? o.hss_steps : (int)(o.hss_m * std::ceil(k));
+        h->cycles = o.mg_cycles > 0 ? o.mg_cycles : 2;
+        h->cycles_auto = o.mg_cycles == 0;
         h->restart = o.restart > 0 ? o.restart : std::min(2000, 3 * (int)std::ceil(k) + 30);
         h->max_outer = o.max_outer > 0 ? o.max_outer : 4 * h->restart;
         for (int l = 0; l < h->levels; ++l) {
@@ -752,12 +1050,16 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
             return HELM_ENOMEM;
         }
         HIPCHK(hipMemcpy(h->d_cinv, Ah.data(), sizeof(cxd) * Ah.size(), hipMemcpyHostToDevice));
+        // private stream used only to capture the preconditioner graph
+        HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     } catch (const DevErr&) {
         if (h->d_cinv) (void)hipFree(h->d_cinv);
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         delete h;
         return HELM_EDEVICE;
     } catch (const std::bad_alloc&) {
         if (h->d_cinv) (void)hipFree(h->d_cinv);
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         delete h;
         return HELM_ENOMEM;
     }
@@ -770,6 +1072,9 @@ int helm_destroy(helm_t* h) {
     int rc = HELM_OK;
     if (hipStreamSynchronize(h->stream) != hipSuccess) rc = HELM_EDEVICE;
     if (h->d_cinv && hipFree(h->d_cinv) != hipSuccess) rc = HELM_EDEVICE;
+    for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return rc;
 }
@@ -978,14 +1283,9 @@ int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs, void* wor
     const long long N = h->Nl[0];
     const Layout Lw = layout(h, nrhs);
     try {
-        if (prec == HELM_FP64)
-            vcycle<double>(h, Lw, workspace, 0, Vec<const cxd>{static_cast<const cxd*>(b), N, 0, nullptr},
-                           Vec<cxd>{static_cast<cxd*>(x), N, 0, nullptr},
-                           at_ws<cxd>(workspace, Lw.mg_t[0], N), nrhs);
-        else
-            vcycle<float>(h, Lw, workspace, 0, Vec<const cxf>{static_cast<const cxf*>(b), N, 0, nullptr},
-                          Vec<cxf>{static_cast<cxf*>(x), N, 0, nullptr},
-                          at_ws<cxf>(workspace, Lw.mg_t[0], N), nrhs);
+        (void)N;
+        if (prec == HELM_FP64) vcycle_entry<double>(h, Lw, workspace, b, x, nrhs);
+        else vcycle_entry<float>(h, Lw, workspace, b, x, nrhs);
         HIPCHK(hipGetLastError());
     } catch (const DevErr&) {
         return HELM_EDEVICE;
@@ -1000,9 +1300,11 @@ int helm_precondition(helm_t* h, const void* v, void* z, int nrhs, void* workspa
     try {
         Vec<const cxd> vv{static_cast<const cxd*>(v), N, 0, nullptr};
         if (h->prec == HELM_FP64) {
+            ensure_cycles<double>(h, Lw, workspace);
             precondition<double>(h, Lw, workspace, vv, Vec<cxd>{static_cast<cxd*>(z), N, 0, nullptr},
                                  nrhs);
         } else {
+            ensure_cycles<float>(h, Lw, workspace);
             precondition<float>(h, Lw, workspace, vv, at_ws<cxf>(workspace, Lw.Z, N), nrhs);
             copy_cast<double, float>(h->stream, N, cst(at_ws<cxf>(workspace, Lw.Z, N)),
                                      Vec<cxd>{static_cast<cxd*>(z), N, 0, nullptr}, nrhs);

@@ -75,13 +75,13 @@ __global__ __launch_bounds__(BS) void k_copy_cast(long long N, Vec<const cx<TI>>
 }
 
 template <typename T>
-__global__ __launch_bounds__(BS) void k_axpy1(long long N, Vec<const cx<T>> X, Vec<cx<T>> Y,
-                                              unsigned gx) {
+__global__ __launch_bounds__(BS) void k_axpy1(long long N, T alpha, Vec<const cx<T>> X,
+                                              Vec<cx<T>> Y, unsigned gx) {
     const int slot = blockIdx.x / gx;
     const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
     if (t >= N) return;
     cx<T>* y = Y.at(slot);
-    y[t] = y[t] + X.at(slot)[t];
+    y[t] = y[t] + alpha * X.at(slot)[t];
 }
 
 __global__ __launch_bounds__(BS) void k_scale_inv(long long N, Vec<const cxd> X, Vec<cxd> Y,
@@ -250,9 +250,9 @@ void copy_cast(hipStream_t st, long long N, Vec<const cx<TI>> X, Vec<cx<TO>> Y, 
 }
 
 template <typename T>
-void axpy1(hipStream_t st, long long N, Vec<const cx<T>> X, Vec<cx<T>> Y, int nslots) {
+void axpy1(hipStream_t st, long long N, T alpha, Vec<const cx<T>> X, Vec<cx<T>> Y, int nslots) {
     const unsigned gx = blocks(N);
-    k_axpy1<T><<<gx * nslots, BS, 0, st>>>(N, X, Y, gx);
+    k_axpy1<T><<<gx * nslots, BS, 0, st>>>(N, alpha, X, Y, gx);
 }
 
 void scale_inv(hipStream_t st, long long N, Vec<const cxd> X, Vec<cxd> Y, const double* div,
@@ -303,8 +303,8 @@ template void copy_cast<double, double>(hipStream_t, long long, Vec<const cxd>, 
 template void copy_cast<float, double>(hipStream_t, long long, Vec<const cxd>, Vec<cxf>, int);
 template void copy_cast<double, float>(hipStream_t, long long, Vec<const cxf>, Vec<cxd>, int);
 template void copy_cast<float, float>(hipStream_t, long long, Vec<const cxf>, Vec<cxf>, int);
-template void axpy1<double>(hipStream_t, long long, Vec<const cxd>, Vec<cxd>, int);
-template void axpy1<float>(hipStream_t, long long, Vec<const cxf>, Vec<cxf>, int);
+template void axpy1<double>(hipStream_t, long long, double, Vec<const cxd>, Vec<cxd>, int);
+template void axpy1<float>(hipStream_t, long long, float, Vec<const cxf>, Vec<cxf>, int);
 template void update_solution<double>(hipStream_t, long long, int, Vec<const cxd>, const cxd*,
                                       int, Vec<cxd>, int);
 template void update_solution<float>(hipStream_t, long long, int, Vec<const cxf>, const cxd*,

@@ -25,6 +25,45 @@ void resid_restrict2d(hipStream_t st, const Op2<T>& op, Vec<const cx<T>> X, Vec<
 template <typename T>
 void prolong2d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslots);
 
+// ---- fused 2D multigrid kernels (kernels2d_fused.hip) ----------------------
+// x = two Jacobi sweeps for L x = b from x = 0
+template <typename T>
+void pre0_2d(hipStream_t st, const Op2<T>& L, Vec<const cx<T>> B, Vec<cx<T>> X, int ns);
+// rho = c (R - B_shift u) (u = 0 when U.base is null), written; then x as
+// in pre0_2d with b = rho
+template <typename T>
+void hss_pre0_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<const cx<T>> U,
+                 Vec<const cx<T>> R, Vec<cx<T>> Rho, Vec<cx<T>> X, int ns);
+// x_out = S Jacobi sweeps from x_in (+ P e_c when Ec.base is set); with
+// update, x_out += result instead.  S in {1, 2, 4}.
+template <typename T>
+void sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin, Vec<const cx<T>> Ec,
+               Vec<const cx<T>> B, Vec<cx<T>> Xout, bool update, int ns);
+
+// as pre0_2d / hss_pre0_2d, and also b_c = P^T (b - L x) on the n/2 mesh
+template <typename T>
+void pre0r_2d(hipStream_t st, const Op2<T>& L, Vec<const cx<T>> B, Vec<cx<T>> X, Vec<cx<T>> Bc,
+              int ns);
+template <typename T>
+void hss_pre0r_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<const cx<T>> U,
+                  Vec<const cx<T>> R, Vec<cx<T>> Rho, Vec<cx<T>> X, Vec<cx<T>> Bc, int ns);
+
+// ---- small-level V-cycle in LDS (kernels2d_small.hip) ---------------------
+// Levels 0..nlev-1 of this record are consecutive mesh levels; the last is
+// the coarsest (solved with the dense FP64 inverse).  Offsets are in
+// complex elements of the dynamic LDS arena; t is shared by all levels.
+constexpr int MAX_SMALL = 8;
+template <typename T>
+struct SmallCycle {
+    int nlev;
+    int n[MAX_SMALL];
+    Op2<T> op[MAX_SMALL];
+    int off_b[MAX_SMALL], off_x[MAX_SMALL], off_t[MAX_SMALL];
+};
+template <typename T>
+void vcycle_small(hipStream_t st, const SmallCycle<T>& sc, size_t lds_bytes, const cxd* Ainv,
+                  int nc, Vec<const cx<T>> B, Vec<cx<T>> X, int ns);
+
 // ---- 3D Q1 stencils (kernels3d.hip) ---------------------------------------
 template <typename T, typename TI>
 void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>> X,
@@ -42,9 +81,9 @@ void coarse_apply(hipStream_t st, const cxd* Ainv, int nc, Vec<const cx<T>> B, V
 // y = x (type conversion allowed)
 template <typename TO, typename TI>
 void copy_cast(hipStream_t st, long long N, Vec<const cx<TI>> X, Vec<cx<TO>> Y, int nslots);
-// y += x
+// y += alpha x
 template <typename T>
-void axpy1(hipStream_t st, long long N, Vec<const cx<T>> X, Vec<cx<T>> Y, int nslots);
+void axpy1(hipStream_t st, long long N, T alpha, Vec<const cx<T>> X, Vec<cx<T>> Y, int nslots);
 // y = alpha x, alpha real per slot: y = x / div[slot]  (div read on device)
 void scale_inv(hipStream_t st, long long N, Vec<const cxd> X, Vec<cxd> Y, const double* div,
                int div_stride, int nslots);

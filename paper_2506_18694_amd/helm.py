@@ -47,7 +47,9 @@ class helm_bc(ctypes.Structure):
 class helm_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("omega", ctypes.c_double), ("hss_m", ctypes.c_int), ("hss_steps", ctypes.c_int),
-                ("restart", ctypes.c_int), ("max_outer", ctypes.c_int), ("x0_given", ctypes.c_int)]
+                ("restart", ctypes.c_int), ("max_outer", ctypes.c_int), ("x0_given", ctypes.c_int),
+                ("profile", ctypes.c_int), ("mg_cycles", ctypes.c_int),
+                ("no_graphs", ctypes.c_int), ("no_small", ctypes.c_int)]
 
 
 class helm_stats(ctypes.Structure):
@@ -55,7 +57,9 @@ class helm_stats(ctypes.Structure):
                 ("hss_steps", ctypes.c_int), ("vcycles", ctypes.c_longlong),
                 ("converged", ctypes.c_int), ("arnoldi_rel_residual", ctypes.c_double),
                 ("true_rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double),
-                ("precond_ms", ctypes.c_double)]
+                ("precond_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double),
+                ("sweep_launches", ctypes.c_longlong), ("sweep_bytes", ctypes.c_double),
+                ("mg_cycles", ctypes.c_int), ("vcycle_rate", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -132,7 +136,8 @@ class Solver:
 
     def __init__(self, dim, n, levels, k, delta=0.0, delta_hat=None, precision="fp64",
                  restart=0, max_outer=0, hss_steps=0, hss_m=1, omega=2.0 / 3.0,
-                 dirichlet_faces=0, stream=None):
+                 dirichlet_faces=0, profile=False, mg_cycles=0, graphs=True, small_kernel=True,
+                 stream=None):
         import torch
         self.torch = torch
         L = lib()
@@ -142,6 +147,10 @@ class Solver:
         opts.precision = HELM_FP64 if precision == "fp64" else HELM_FP32_MG
         opts.restart, opts.max_outer = restart, max_outer
         opts.hss_steps, opts.hss_m, opts.omega = hss_steps, hss_m, omega
+        opts.profile = 1 if profile else 0
+        opts.mg_cycles = mg_cycles
+        opts.no_graphs = 0 if graphs else 1
+        opts.no_small = 0 if small_kernel else 1
         bc = helm_bc(dirichlet_faces)
         if stream is None:
             stream = torch.cuda.current_stream()

@@ -132,14 +132,36 @@ def test_vcycle_matches_oracle(dim, n, levels, k, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 5e-4)])
-@pytest.mark.parametrize("dim,n,levels,k", [(2, 64, 3, 10.0), (2, 48, 2, 7.3), (3, 8, 2, 3.0)])
-def test_preconditioner_matches_oracle(dim, n, levels, k, prec, tol):
-    s = _solver(dim, n, levels, k, k, prec, restart=4)
-    pr = osolver.Problem(dim, n, k, k, levels=levels)
+@pytest.mark.parametrize("dim,n,levels,k,cycles", [
+    (2, 64, 3, 10.0, 2), (2, 48, 2, 7.3, 3), (2, 96, 4, 12.0, 1), (2, 16, 1, 4.0, 2),
+    (2, 34, 2, 1.0, 3), (3, 8, 2, 3.0, 2)])
+def test_preconditioner_matches_oracle(dim, n, levels, k, cycles, prec, tol):
+    s = _solver(dim, n, levels, k, k, prec, restart=4, mg_cycles=cycles)
+    pr = osolver.Problem(dim, n, k, k, levels=levels, cycles=cycles)
     v = W.random_complex((3, s.nodes(0)), 5)
     z = to_host(s.precondition(to_dev(v)))
     ref = np.stack([pr.precond(vi, inner="mg") for vi in v])
     assert rel_l2(z, ref) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-4)])
+@pytest.mark.parametrize("n,levels,k", [(128, 5, 12.0), (96, 4, 9.0), (256, 6, 20.0)])
+def test_paths_agree_and_match_oracle(n, levels, k, prec, tol):
+    """The LDS-resident small-level cycle, the per-level kernels and the
+    unfused one-pass-per-launch path (the profiled solve) all compute the
+    same preconditioner as the oracle; graphs on and off agree."""
+    pr = osolver.Problem(2, n, k, k, levels=levels, cycles=2)
+    v = W.random_complex((2, (n + 1) ** 2), 17)
+    ref = np.stack([pr.precond(vi, inner="mg") for vi in v])
+    outs = []
+    for small, graphs in ((True, True), (False, True), (True, False)):
+        s = _solver(2, n, levels, k, k, prec, restart=4, mg_cycles=2, small_kernel=small,
+                    graphs=graphs)
+        outs.append(to_host(s.precondition(to_dev(v))))
+        s.close()
+    for z in outs:
+        assert rel_l2(z, ref) < tol * 5
+    assert rel_l2(outs[0], outs[2]) < 1e-14  # graph replay is bit-for-bit the eager path
 
 
 def test_load_nodal_is_mass_times_source():

@@ -40,6 +40,11 @@ def test_cycle_error_propagator(dim, n, levels, k):
     xtrue = W.random_complex(Nn, 5)
     x = multigrid.vcycle(h, A @ xtrue)
     assert np.linalg.norm((xtrue - x) - E @ xtrue) < 1e-10 * np.linalg.norm(xtrue)
+    # q cycles as a stationary iteration propagate the error by E^q
+    for q in (2, 3):
+        xq = multigrid.cycles(h, A @ xtrue, q)
+        Eq = np.linalg.matrix_power(E, q)
+        assert np.linalg.norm((xtrue - xq) - Eq @ xtrue) < 1e-10 * np.linalg.norm(xtrue)
     # linearity
     b1, b2 = W.random_complex(Nn, 6), W.random_complex(Nn, 7)
     lhs = multigrid.vcycle(h, (2 - 1j) * b1 + b2)
