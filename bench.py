@@ -2,8 +2,9 @@
 relative residual for the shifted-HSS Helmholtz solver on one MI355X.
 
 One step = one complete helm_solve (outer FP64 FGMRES, shifted-HSS
-preconditioner with ceil(k) HSS sweeps, one V(2,2) cycle per sweep, all
-right-hand sides) with the load vectors already resident in HBM.
+preconditioner with ceil(k) HSS sweeps, each inner solve a fixed number of
+V(2,2) cycles chosen from the measured cycle rate, all right-hand sides)
+with the load vectors already resident in HBM.
 
 Default workload: 2D P1, 1024 x 1024 right-diagonal mesh (N = 1,050,625
 nodes), k = 100, delta = 0, delta_hat = k, 8 multigrid levels, four
@@ -35,7 +36,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels2d.hip", "helm_common.h", "stencil_rows.h"):
+    for f in ("kernels2d_fused.hip", "helm_common.h", "stencil_rows.h"):
         with open(os.path.join(ROOT, "paper_2506_18694_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -44,7 +45,7 @@ def kernel_source_hash():
 def stored_traffic(workload, precision):
     """HBM traffic per launch of the dominant kernel from committed rocprofv3
     counter runs; null when the kernel source changed since they were taken."""
-    path = os.path.join(PROFILES, "traffic_jacobi_%s_%s.json" % (workload, precision))
+    path = os.path.join(PROFILES, "traffic_k_sweeps4_%s_%s.json" % (workload, precision))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -54,12 +55,13 @@ def stored_traffic(workload, precision):
     return rec.get("bytes_per_launch")
 
 
-def run_solves(W, name, precision, steps, warmup, tol):
+def run_solves(W, name, precision, steps, warmup, tol, max_outer=0):
     import torch
     from paper_2506_18694_amd import Solver
     w = W.WORKLOADS[name]
     s = Solver(w["dim"], w["n"], w["levels"], w["k"], w["delta"], w["delta_hat"],
-               precision=precision, profile=True)
+               precision=precision, profile=True, max_outer=max_outer,
+               restart=max_outer if max_outer else 0)
     f = torch.from_numpy(W.workload_sources(name)).cuda().contiguous()
     b = s.load_nodal(f)
     x = torch.empty_like(b)
@@ -85,39 +87,44 @@ def run_solves(W, name, precision, steps, warmup, tol):
     return dict(N=s.N, nrhs=b.shape[0], elapsed=elapsed, stats=stats, ok=ok, w=w)
 
 
-def cpu_baseline(W, name, outer_its, sample_steps):
-    """The oracle's HSS sweep (one CSR V-cycle per step, correction form) timed
-    on the host for one right-hand side, extrapolated to a full solve with the
-    GPU's outer iteration count."""
-    import numpy as np
+def cpu_baseline(W, name, outer_its, cycles, sample_steps):
+    """The oracle's HSS step (correction form, `cycles` CSR V(2,2) cycles per
+    inner solve, as the GPU run used) timed on the host for one right-hand
+    side, extrapolated to the full solve with the GPU's outer iteration count
+    (the oracle's own FGMRES orthogonalisation is left out, which flatters
+    the CPU)."""
     from oracle import solver as osolver, hss
     w = W.WORKLOADS[name]
-    pr = osolver.Problem(w["dim"], w["n"], w["k"], w["delta_hat"], levels=w["levels"])
+    pr = osolver.Problem(w["dim"], w["n"], w["k"], w["delta_hat"], levels=w["levels"],
+                         cycles=cycles)
     f = W.workload_sources(name)[0]
     R = pr.M @ f
     _ = pr.hierarchy
     t0 = time.perf_counter()
-    hss.hss_correction(pr.Bdh, R, w["k"], sample_steps, pr.vcycle)
+    hss.hss_correction(pr.Bdh, R, w["k"], sample_steps, pr.mg_solve)
     t_step = (time.perf_counter() - t0) / sample_steps
     nrhs = w["nrhs"]
     t_solve = nrhs * outer_its * pr.hss_steps() * t_step
     N = (w["n"] + 1) ** w["dim"]
     return {"value": N * nrhs / t_solve, "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": "%d HSS steps (CSR V(2,2) each) for 1 of %d right-hand sides on the %s mesh, "
-                      "%.3f s per step, extrapolated to %d outer its x %d steps x %d rhs"
-                      % (sample_steps, nrhs, name, t_step, outer_its, pr.hss_steps(), nrhs)}
+            "sample": "%d HSS steps (%d CSR V(2,2) cycles each) for 1 of %d right-hand sides on "
+                      "the %s mesh, %.3f s per step, extrapolated to %d outer its x %d steps x "
+                      "%d rhs" % (sample_steps, cycles, nrhs, name, t_step, outer_its,
+                                  pr.hss_steps(), nrhs)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="p1-1024-k100")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for counter collection: 3 outer iterations, no extras")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X and "
@@ -132,7 +139,10 @@ def main():
     name = args.workload
     prec = W.WORKLOADS[name]["precision"]
     main_prec = "fp64" if prec == "fp64" else "fp32"
-    r = run_solves(W, name, main_prec, args.steps, args.warmup, args.tol)
+    if args.profile_run:
+        args.no_fp32 = args.no_cpu_baseline = True
+    r = run_solves(W, name, main_prec, args.steps, args.warmup, args.tol,
+                   max_outer=3 if args.profile_run else 0)
     ms = r["elapsed"] / args.steps * 1e3
     value = r["N"] * r["nrhs"] / (ms / 1e3)
     sw_ms = sum(st["sweep_ms"] for st in r["stats"])
@@ -143,7 +153,7 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": stored_traffic(name, main_prec),
-            "kernel": "finest-level Jacobi sweep (k_stencil2d, MODE_JACOBI)",
+            "kernel": "finest-level prolongation + four Jacobi sweeps (k_sweeps<S=4>)",
             "bytes_per_launch": per_launch,
             "avg_launch_us": sw_ms / sw_n * 1e3 if sw_n else None}
     w = r["w"]
@@ -157,6 +167,8 @@ def main():
                       "levels": w["levels"], "precision": main_prec, "tol": args.tol,
                       "outer_its": max(st["outer_its"] for st in r["stats"]),
                       "hss_steps": r["stats"][0]["hss_steps"],
+                      "mg_cycles": r["stats"][0]["mg_cycles"],
+                      "vcycle_rate": r["stats"][0]["vcycle_rate"],
                       "true_rel_residual": max(st["true_rel_residual"] for st in r["stats"]),
                       "converged": r["ok"]},
            "roofline": roof}
@@ -174,7 +186,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline sample ...")
         out["cpu_baseline"] = cpu_baseline(W, name, out["config"]["outer_its"],
-                                           args.cpu_sample_steps)
+                                           out["config"]["mg_cycles"], args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -93,6 +93,10 @@ Op2<T> make_op2(const Coef& cf, int n, double omega) {
     o.wAx = tocx<T>(wAx);
     o.wDg = tocx<T>(wDg);
     o.odC = tocx<T>(omega / wC);
+    // edge, corner (0,0)/(n,n) and corner (n,0)/(0,n) diagonals (see Op2)
+    o.odE = tocx<T>(omega / (2.0 * A + 6.0 * Bm + 4.0 * Cg));
+    o.odA = tocx<T>(omega / (A + 4.0 * Bm + 4.0 * Cg));
+    o.odB = tocx<T>(omega / (A + 2.0 * Bm + 4.0 * Cg));
     o.omega = (T)omega;
     o.n = n;
     return o;
@@ -368,7 +372,8 @@ template <typename T>
 int small_start(const helm_t* h) {
     if (h->dim != 2 || h->levels < 2 || h->nc > 289 || h->opts.no_small) return -1;
     for (int l = 1; l < h->levels - 1; ++l) {
-        size_t elems = (size_t)h->Nl[l];  // shared scratch, sized for level l
+        // shared scratch sized for level l and the coarse-solve partials
+        size_t elems = std::max((size_t)h->Nl[l], 1024 * sizeof(cxd) / sizeof(cx<T>)) + 1;
         for (int m = l; m < h->levels; ++m) elems += 2 * (size_t)h->Nl[m];
         if (elems * sizeof(cx<T>) <= 65536 && h->levels - l <= MAX_SMALL) return l;
     }
@@ -389,8 +394,11 @@ void run_small(helm_t* h, int l0, Vec<const cx<T>> b, Vec<cx<T>> x, int ns) {
         sc.off_x[m] = off;
         off += (int)h->Nl[lev];
     }
+    // shared scratch: the largest level's vector, and room for 1024 FP64
+    // complex partial sums of the coarse solve; 16-byte aligned
+    off += off & 1;
     for (int m = 0; m < sc.nlev; ++m) sc.off_t[m] = off;
-    off += (int)h->Nl[l0];
+    off += std::max((int)h->Nl[l0], 1024 * (int)(sizeof(cxd) / sizeof(cx<T>)));
     vcycle_small<T>(h->stream, sc, sizeof(cx<T>) * (size_t)off, h->d_cinv, h->nc, b, x, ns);
 }
 

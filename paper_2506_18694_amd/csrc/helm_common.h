@@ -77,14 +77,27 @@ inline Vec<V> contiguous(V* p, long long n) { return Vec<V>{p, n, 0, nullptr}; }
 // and edge matrices); wC/wAx/wDg are the interior weights of the centre,
 // the four axis neighbours and the two "/" diagonal neighbours;
 // odC = omega / wC is the interior Jacobi factor.
+// The diagonal takes four values: interior, edge (any side), and the two
+// corner types of the right-diagonal mesh ((0,0)/(n,n) touch two triangles,
+// (n,0)/(0,n) one), so the Jacobi factors omega / D are precomputed:
+// odC interior, odE edge, odA corners (0,0)/(n,n), odB corners (n,0)/(0,n).
 template <typename T>
 struct Op2 {
     cx<T> A, Bm, Cg;
     cx<T> wC, wAx, wDg;
-    cx<T> odC;
+    cx<T> odC, odE, odA, odB;
     T omega;
     int n;
 };
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> jacobi_factor(const Op2<T>& op, int i, int j) {
+    const int n = op.n;
+    const bool ei = (i == 0) | (i == n), ej = (j == 0) | (j == n);
+    if (!(ei | ej)) return op.odC;
+    if (!(ei & ej)) return op.odE;
+    return ((i == 0) == (j == 0)) ? op.odA : op.odB;
+}
 
 // Stencil record on one 3D Q1 level: 1D factors of the tensor-product
 // element matrices.  K1 = (1/h)[-1 2 -1], M1 = (h/6)[1 4 1], boundary rows

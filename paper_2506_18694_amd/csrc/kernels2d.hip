@@ -76,13 +76,7 @@ __global__ __launch_bounds__(BS) void k_stencil2d(Op2<T> op, T s, Vec<const cx<T
     cx<T>* y = Y.at(slot);
     if (MODE == MODE_JACOBI0) {
         const cx<T>* b = B.at(slot);
-        cx<T> f;
-        if (interior) {
-            f = op.odC;
-        } else {
-            Row7<T> r = row_weights(op, i, j);
-            f = cdiv(mk(op.omega, (T)0), r.w[0]);
-        }
+        const cx<T> f = interior ? op.odC : jacobi_factor(op, i, j);
         y[t] = f * b[t];
         return;
     }
@@ -101,7 +95,7 @@ __global__ __launch_bounds__(BS) void k_stencil2d(Op2<T> op, T s, Vec<const cx<T
     } else {  // MODE_JACOBI
         const cx<T>* b = B.at(slot);
         cx<T> r = b[t] - lx;
-        cx<T> f = interior ? op.odC : cdiv(mk(op.omega, (T)0), d);
+        const cx<T> f = interior ? op.odC : jacobi_factor(op, i, j);
         y[t] = cfma(f, r, ld<T>(x, t));
     }
 }

@@ -29,9 +29,7 @@ __device__ __forceinline__ cx<T> czero() { return mk((T)0, (T)0); }
 // Jacobi factor omega / D at node (i, j)
 template <typename T>
 __device__ __forceinline__ cx<T> jac_factor(const Op2<T>& op, int i, int j, bool interior) {
-    if (interior) return op.odC;
-    Row7<T> r = row_weights(op, i, j);
-    return cdiv(mk(op.omega, (T)0), r.w[0]);
+    return interior ? op.odC : jacobi_factor(op, i, j);
 }
 
 // (Op x) at node (i, j) with x read from an LDS region of width W whose

@@ -47,9 +47,7 @@ __device__ __forceinline__ cx<T> apply_level(const Op2<T>& op, const cx<T>* s, i
 
 template <typename T>
 __device__ __forceinline__ cx<T> jfac(const Op2<T>& op, int i, int j) {
-    const int n = op.n;
-    if (i > 0 && i < n && j > 0 && j < n) return op.odC;
-    return cdiv(mk(op.omega, (T)0), row_weights(op, i, j).w[0]);
+    return jacobi_factor(op, i, j);
 }
 
 template <typename T>
@@ -100,26 +98,47 @@ __global__ __launch_bounds__(NTS) void k_vcycle_small(SmallCycle<T> sc, const cx
         }
         __syncthreads();
     }
-    // coarsest: x = Ainv b in FP64, one wavefront per row
+    // coarsest: x = Ainv b in FP64.  Thread (r, g) forms the partial sum of
+    // row r over the columns g, g + G, ...; its loads are issued in batches
+    // of eight so that they are in flight together.  Partials meet in the
+    // scratch area (at least NTS FP64 complex values), then one thread per
+    // row adds its G partials in a fixed order.
     {
         const cx<T>* B = lds + sc.off_b[L - 1];
         cx<T>* X = lds + sc.off_x[L - 1];
-        const int lane = tid % WAVE, wv = tid / WAVE;
-        for (int r = wv; r < nc; r += NTS / WAVE) {
+        cxd* part = reinterpret_cast<cxd*>(lds + sc.off_t[0]);
+        const int G = nc < NTS ? NTS / nc : 1;
+        const int r = tid / G, g = tid % G;
+        if (r < nc) {
             const cxd* a = Ainv + (long long)r * nc;
             double re = 0.0, im = 0.0;
-            for (int cc = lane; cc < nc; cc += WAVE) {
-                const cxd bv = cvt<double>(B[cc]);
-                const cxd av = a[cc];
-                re = fma(av.x, bv.x, fma(-av.y, bv.y, re));
-                im = fma(av.x, bv.y, fma(av.y, bv.x, im));
-            }
+            for (int c0 = g; c0 < nc; c0 += 8 * G) {
+                cxd av[8];
 #pragma unroll
-            for (int o = WAVE / 2; o > 0; o >>= 1) {
-                re += __shfl_xor(re, o, WAVE);
-                im += __shfl_xor(im, o, WAVE);
+                for (int u = 0; u < 8; ++u) {
+                    const int cc = c0 + u * G;
+                    av[u] = cc < nc ? a[cc] : mk(0.0, 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int cc = c0 + u * G;
+                    if (cc < nc) {
+                        const cxd bv = cvt<double>(B[cc]);
+                        re = fma(av[u].x, bv.x, fma(-av[u].y, bv.y, re));
+                        im = fma(av[u].x, bv.y, fma(av[u].y, bv.x, im));
+                    }
+                }
             }
-            if (lane == 0) X[r] = mk((T)re, (T)im);
+            part[tid] = mk(re, im);
+        }
+        __syncthreads();
+        if (tid < nc) {
+            double re = 0.0, im = 0.0;
+            for (int q = 0; q < G; ++q) {
+                re += part[tid * G + q].x;
+                im += part[tid * G + q].y;
+            }
+            X[tid] = mk((T)re, (T)im);
         }
     }
     __syncthreads();

@@ -13,9 +13,9 @@ Sommerfeld conditions on every face and V(2,2) scaled Jacobi, omega = 2/3):
                    one Gaussian at (0.5, 0.5), sigma 0.05, complex FP64
   p1-1024-k100     2D P1, 1024 x 1024, k = 100, 8 levels, four Gaussians at
                    seeded uniform centres (PCG64 seed 0), sigma 0.02, FP64
-  p1-2048-k200     2D P1, 2048 x 2048, k = 200, 8 levels (coarsest 16 x 16),
-                   Gaussian at (0.5, 0.5), sigma 0.05, FP32 multigrid with
-                   FP64 outer iteration
+  p1-2048-k200     2D P1, 2048 x 2048, k = 200, 9 levels (coarsest 8 x 8, as
+                   for the 1024 mesh), Gaussian at (0.5, 0.5), sigma 0.05,
+                   FP32 multigrid with FP64 outer iteration
   q1-256-k40       3D Q1, 256^3 hexahedra, k = 40, 6 levels, one Gaussian at a
                    seeded uniform centre (seed 0), sigma 0.03, FP32 multigrid
 The paper's own sources (uniform f = 1 and the box source on
@@ -29,7 +29,7 @@ WORKLOADS = {
                       nrhs=1, precision="fp64", sigma=0.05, centres="centre"),
     "p1-1024-k100": dict(dim=2, n=1024, k=100.0, delta=0.0, delta_hat=100.0, levels=8,
                          nrhs=4, precision="fp64", sigma=0.02, centres="seed0"),
-    "p1-2048-k200": dict(dim=2, n=2048, k=200.0, delta=0.0, delta_hat=200.0, levels=8,
+    "p1-2048-k200": dict(dim=2, n=2048, k=200.0, delta=0.0, delta_hat=200.0, levels=9,
                          nrhs=1, precision="fp32mg", sigma=0.05, centres="centre"),
     "q1-256-k40": dict(dim=3, n=256, k=40.0, delta=0.0, delta_hat=40.0, levels=6,
                        nrhs=1, precision="fp32mg", sigma=0.03, centres="seed0"),
