@@ -120,6 +120,8 @@ typedef struct {
                           default the levels from the first one whose
                           vectors fit one workgroup's LDS down to the
                           coarsest run as one LDS-resident kernel per cycle  */
+    int    verbose;    /* > 0: print the Arnoldi residual estimate to stderr
+                          every `verbose` outer iterations                   */
 } helm_opts;
 
 typedef struct {
@@ -252,6 +254,62 @@ int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs,
  * precision mode.  v, z: complex FP64 [nrhs][N]. */
 int helm_precondition(helm_t* h, const void* v, void* z, int nrhs,
                       void* workspace);
+
+/* ---- serving: continuous batching of independent solves -----------------
+ * A server solves a stream of requests (one mesh, k, delta_hat and a set of
+ * right-hand sides each).  Requests with the same mesh and parameters form a
+ * group that shares one solver handle, one device workspace of `max_cols`
+ * column slots and one stream; every column owns a slot (its own Krylov
+ * basis and iterate).  helm_server_step advances every running column by
+ * one outer FGMRES iteration, all columns of a group in the same kernel
+ * launches, all groups enqueued before any is waited for (so groups overlap
+ * on the device), and admits queued requests into free slots at that step
+ * boundary, creating groups while their workspace fits the HBM budget and
+ * releasing idle groups when space is needed.  A column's arithmetic does
+ * not depend on which other columns share its launches, so a request's
+ * result is the same alone and in the mix.
+ * The server allocates its workspaces itself (hipMalloc) and owns its
+ * streams.  Not thread-safe.
+ */
+typedef struct helm_server_s helm_server_t;
+
+typedef struct {
+    double hbm_budget_bytes;  /* device memory for group workspaces (> 0)      */
+    int    max_cols;          /* column slots per group (>= 1)                 */
+    int    precision;         /* HELM_FP64 or HELM_FP32_MG                     */
+    int    restart;           /* FGMRES basis per column; 0 = 3 ceil(k) + 30   */
+    int    max_outer;         /* 0 = 4 * restart                               */
+} helm_server_opts;
+
+typedef struct {
+    int    status;            /* 0 queued, 1 running, 2 done                   */
+    int    converged;         /* every column met its tolerance                */
+    int    outer_its;         /* max over the request's columns                */
+    double true_rel_residual; /* max over its columns                          */
+    double t_submit, t_admit, t_done;  /* seconds since helm_server_create     */
+} helm_request_info;
+
+int helm_server_create(const helm_server_opts* opts, helm_server_t** out);
+
+/* Queue a request: solve B_0 x = rhs for nrhs columns on the dim-D unit
+ * domain with n cells per side and `levels` multigrid levels, wavenumber k,
+ * shift delta_hat.  rhs, x: device, complex FP64 [nrhs][N], caller-owned;
+ * rhs must stay valid until the request is admitted, x until it is done.
+ * Errors: HELM_EINVAL for invalid sizes or parameters (as helm_create), or
+ * nrhs > max_cols (the request could never be admitted). */
+int helm_server_submit(helm_server_t* s, int dim, int n, int levels, double k, double delta_hat,
+                       const void* rhs, void* x, int nrhs, double tol, long long* id);
+
+/* One step of every running group plus admission; *n_done (nullable)
+ * receives the number of requests completed by this step. */
+int helm_server_step(helm_server_t* s, int* n_done);
+
+int helm_server_query(const helm_server_t* s, long long id, helm_request_info* info);
+
+/* Queued and running request counts and device bytes held in workspaces. */
+int helm_server_load(const helm_server_t* s, int* queued, int* running, double* bytes_in_use);
+
+int helm_server_destroy(helm_server_t* s);
 
 #ifdef __cplusplus
 }

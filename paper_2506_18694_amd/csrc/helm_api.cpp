@@ -234,11 +234,17 @@ namespace {
 constexpr size_t ALIGN = 256;
 inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+// Device workspace for up to `nrhs` columns.  Per column c: the load
+// vector B[c] and iterate X[c] (FP64), the Krylov basis V[c][0..R] (FP64)
+// and the preconditioned directions Z[c][0..R-1] (the preconditioner's
+// storage precision); per slot: the multigrid level vectors and the HSS
+// buffers R and u; plus small reduction and index arrays.
+constexpr int NMAPS = 8;
 struct Layout {
     size_t mg_b[32], mg_x[32], mg_t[32];
     size_t R, u;
-    size_t V, Z;
-    size_t dh, dh2, dnorm, part, npart, dy, cols;
+    size_t V, Z, Bw, Xw;
+    size_t dh, dh2, dnorm, part, npart, dy, cols, maps;
     size_t total;
 };
 
@@ -255,9 +261,10 @@ Layout layout(const helm_t* h, int nrhs) {
     const long long N = h->Nl[0];
     const int nblk = multidot_blocks(N);
     L.cols = take(sizeof(int) * nrhs);
+    L.maps = take(sizeof(int) * NMAPS * nrhs);
     L.dh = take(sizeof(cxd) * nrhs * (R + 1));
     L.dh2 = take(sizeof(cxd) * nrhs * (R + 1));
-    L.dnorm = take(sizeof(double) * nrhs);
+    L.dnorm = take(sizeof(double) * 3 * nrhs);
     L.dy = take(sizeof(cxd) * nrhs * R);
     L.part = take(sizeof(cxd) * (size_t)nrhs * (R + 1) * nblk);
     L.npart = take(sizeof(double) * (size_t)nrhs * nblk);
@@ -270,6 +277,8 @@ Layout layout(const helm_t* h, int nrhs) {
     L.u = take(smg * nrhs * N);
     L.V = take(sizeof(cxd) * (size_t)nrhs * (R + 1) * N);
     L.Z = take(smg * (size_t)nrhs * R * N);
+    L.Bw = take(sizeof(cxd) * (size_t)nrhs * N);
+    L.Xw = take(sizeof(cxd) * (size_t)nrhs * N);
     L.total = off;
     return L;
 }
@@ -625,292 +634,80 @@ void vcycle_entry(helm_t* h, const Layout& Lw, void* ws, const void* b, void* x,
 }
 
 // ----------------------------------------------------------------- FGMRES --
-struct ColState {
-    std::vector<zd> H;  // (R+1) x R column-major: H[i + j*(R+1)]
-    std::vector<zd> cs, sn, g;
-    double bnorm = 0.0, beta = 0.0, est = 0.0;
-    int its = 0;
-    bool done = false;
-};
+#include "fgmres_engine.h"
 
+// helm_solve: every column is admitted at once; steps run until all are done.
 template <typename T>
-int fgmres(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws, helm_stats* st) {
+int solve_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws,
+                  helm_stats* st) {
     const auto t0 = std::chrono::steady_clock::now();
-    hipStream_t s = h->stream;
     const long long N = h->Nl[0];
-    const int R = h->restart;
-    const Layout Lw = layout(h, nrhs);
-    char* wsb = static_cast<char*>(ws);
-    int* d_cols = reinterpret_cast<int*>(wsb + Lw.cols);
-    cxd* d_h = reinterpret_cast<cxd*>(wsb + Lw.dh);
-    cxd* d_h2 = reinterpret_cast<cxd*>(wsb + Lw.dh2);
-    double* d_norm = reinterpret_cast<double*>(wsb + Lw.dnorm);
-    cxd* d_part = reinterpret_cast<cxd*>(wsb + Lw.part);
-    double* d_npart = reinterpret_cast<double*>(wsb + Lw.npart);
-    cxd* d_y = reinterpret_cast<cxd*>(wsb + Lw.dy);
-    cxd* Vb = reinterpret_cast<cxd*>(wsb + Lw.V);
-    cx<T>* Zb = reinterpret_cast<cx<T>*>(wsb + Lw.Z);
-    const int nblk = multidot_blocks(N);
-    const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
-    const Op2<double> B2 = make_op2<double>(b0, h->n, h->omega);
-    const Op3<double> B3 = make_op3<double>(b0, h->n, h->omega);
-
-    // V[c][i] at Vb + (c*(R+1) + i)*N ; Z[c][i] at Zb + (c*R + i)*N
-    auto Vcol = [&](int i, const int* cols) {
-        return Vec<cxd>{Vb, (long long)(R + 1) * N, (long long)i * N, cols};
-    };
-    auto Zcol = [&](int i, const int* cols) {
-        return Vec<cx<T>>{Zb, (long long)R * N, (long long)i * N, cols};
-    };
-    auto Xcol = [&](const int* cols) { return Vec<cxd>{x, N, 0, cols}; };
-    auto Bcol = [&](const int* cols) { return Vec<const cxd>{rhs, N, 0, cols}; };
-    auto apply_B = [&](int mode, Vec<const cxd> X, Vec<const cxd> Bv, Vec<cxd> Y, int ns) {
-        if (h->dim == 2) stencil2d<double, double>(s, B2, mode, 1.0, X, Bv, Y, ns);
-        else stencil3d<double, double>(s, B3, mode, 1.0, X, Bv, Y, ns);
-    };
-    auto apply_BZ = [&](Vec<const cx<T>> Zv, Vec<cxd> Y, int ns) {
-        if (h->dim == 2) stencil2d<double, T>(s, B2, MODE_APPLY, 1.0, Zv, Vec<const cxd>{}, Y, ns);
-        else stencil3d<double, T>(s, B3, MODE_APPLY, 1.0, Zv, Vec<const cxd>{}, Y, ns);
-    };
-
-    std::vector<ColState> cs(nrhs);
-    std::vector<int> all(nrhs);
-    for (int c = 0; c < nrhs; ++c) all[c] = c;
-    HIPCHK(hipMemcpyAsync(d_cols, all.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-    // ||b|| per column
-    norm2(s, N, Bcol(d_cols), d_npart, d_norm, 1, nrhs);
-    std::vector<double> hn(nrhs);
-    HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int c = 0; c < nrhs; ++c) {
-        if (!std::isfinite(hn[c])) {
-            g_last_error = "non-finite right-hand side";
-            return HELM_EINVAL;
-        }
-        cs[c].bnorm = hn[c];
-        cs[c].H.assign((size_t)(R + 1) * R, 0.0);
-        cs[c].cs.assign(R, 0.0);
-        cs[c].sn.assign(R, 0.0);
-        cs[c].g.assign(R + 1, 0.0);
-    }
-    if (!h->opts.x0_given) zero<double>(s, x, N * nrhs);
-
-    ensure_cycles<T>(h, Lw, ws);
+    Engine<T> E;
+    struct Guard {
+        Engine<T>& e;
+        ~Guard() { e.release(); }
+    } guard{E};
+    E.init(h, ws, nrhs, tol);
+    ensure_cycles<T>(h, E.Lw, ws);
     h->prof_on = h->opts.profile != 0;
     h->prof_used = 0;
     h->prof_ms = h->prof_bytes = h->prof_pending_bytes = 0.0;
     h->prof_launches = 0;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    double precond_ms = 0.0;
-    int restarts = 0;
-    long long vcycles = 0;
-    int total_its = 0;
-    std::vector<int> active;
-    std::vector<int> host_cols(nrhs);
-    bool first_cycle = true;
-
-    auto finish_cols = [&](const std::vector<int>& cols_done, int m) {
-        // x_c += Z_c y_c for the listed columns, with y from the triangular solve
-        if (cols_done.empty() || m == 0) return;
-        std::vector<cxd> yb((size_t)cols_done.size() * R);
-        for (size_t q = 0; q < cols_done.size(); ++q) {
-            ColState& C = cs[cols_done[q]];
-            std::vector<zd> y(m);
-            for (int i = m - 1; i >= 0; --i) {
-                zd acc = C.g[i];
-                for (int jj = i + 1; jj < m; ++jj) acc -= C.H[i + (size_t)jj * (R + 1)] * y[jj];
-                y[i] = acc / C.H[i + (size_t)i * (R + 1)];
-            }
-            for (int i = 0; i < m; ++i) yb[q * R + i] = mk(y[i].real(), y[i].imag());
-        }
-        int* d_c2 = d_cols;  // reuse: upload the finishing set
-        HIPCHK(hipMemcpyAsync(d_c2, cols_done.data(), sizeof(int) * cols_done.size(),
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d_y, yb.data(), sizeof(cxd) * yb.size(), hipMemcpyHostToDevice, s));
-        update_solution<T>(s, N, m, cst(Zcol(0, d_c2)), d_y, R, Xcol(d_c2), (int)cols_done.size());
-        HIPCHK(hipStreamSynchronize(s));
-    };
-
-    for (;;) {
-        // ---- (re)start: r = b - B x for unconverged columns, V_0 = r/||r||
-        active.clear();
-        for (int c = 0; c < nrhs; ++c)
-            if (!cs[c].done && cs[c].its < h->max_outer) active.push_back(c);
-        if (active.empty()) break;
-        int ns = (int)active.size();
-        HIPCHK(hipMemcpyAsync(d_cols, active.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
-        if (first_cycle && !h->opts.x0_given) {
-            copy_cast<double, double>(s, N, Bcol(d_cols), Vcol(0, d_cols), ns);
-        } else {
-            apply_B(MODE_RESID, cst(Xcol(d_cols)), Bcol(d_cols), Vcol(0, d_cols), ns);
-        }
-        norm2(s, N, cst(Vcol(0, d_cols)), d_npart, d_norm, 1, ns);
-        HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        {
-            std::vector<int> still;
-            for (int q = 0; q < ns; ++q) {
-                ColState& C = cs[active[q]];
-                C.beta = hn[q];
-                C.est = C.bnorm > 0 ? hn[q] / C.bnorm : 0.0;
-                if (C.bnorm == 0.0 || hn[q] <= tol * C.bnorm) {
-                    C.done = true;
-                } else {
-                    still.push_back(active[q]);
+    for (int c = 0; c < nrhs; ++c)
+        E.admit(c, rhs + (long long)c * N, h->opts.x0_given ? x + (long long)c * N : nullptr, tol);
+    int steps = 0;
+    while (E.enqueue()) {
+        E.complete();
+        if (steps++ == 0) {
+            for (const auto& C : E.col)
+                if (C.have_bnorm && !std::isfinite(C.bnorm)) {
+                    g_last_error = "non-finite right-hand side";
+                    h->prof_on = false;
+                    return HELM_EINVAL;
                 }
-            }
-            if (still.empty()) break;
-            if (!first_cycle) ++restarts;
-            first_cycle = false;
-            // scale V_0 of the still-active columns: order norms as `still`
-            std::vector<double> bn;
-            for (int c : still) bn.push_back(cs[c].beta);
-            active = still;
-            ns = (int)active.size();
-            HIPCHK(hipMemcpyAsync(d_cols, active.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_norm, bn.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
-            scale_inv(s, N, cst(Vcol(0, d_cols)), Vcol(0, d_cols), d_norm, 1, ns);
-            for (int c : active) {
-                ColState& C = cs[c];
-                std::fill(C.g.begin(), C.g.end(), zd(0.0));
-                C.g[0] = C.beta;
-            }
         }
-        int m_done = 0;
-        for (int j = 0; j < R; ++j) {
-            ns = (int)active.size();
-            // z_j = B~^{-1} v_j
-            HIPCHK(hipEventRecord(e0, s));
-            precondition<T>(h, Lw, ws, cst(Vcol(j, d_cols)), Zcol(j, d_cols), ns);
-            HIPCHK(hipEventRecord(e1, s));
-            vcycles += (long long)ns * h->hss_steps;
-            // w = B z_j into V_{j+1}
-            apply_BZ(cst(Zcol(j, d_cols)), Vcol(j + 1, d_cols), ns);
-            // classical Gram-Schmidt, twice
-            for (int pass = 0; pass < 2; ++pass) {
-                cxd* hd = pass == 0 ? d_h : d_h2;
-                multidot(s, N, j + 1, cst(Vcol(0, d_cols)), cst(Vcol(j + 1, d_cols)), d_part, ns);
-                reduce_parts(s, j + 1, nblk, d_part, hd, R + 1, 0, ns);
-                multi_axpy(s, N, j + 1, cst(Vcol(0, d_cols)), hd, R + 1, Vcol(j + 1, d_cols), ns);
-            }
-            norm2(s, N, cst(Vcol(j + 1, d_cols)), d_npart, d_norm, 1, ns);
-            scale_inv(s, N, cst(Vcol(j + 1, d_cols)), Vcol(j + 1, d_cols), d_norm, 1, ns);
-            std::vector<cxd> hh((size_t)ns * (R + 1)), hh2((size_t)ns * (R + 1));
-            HIPCHK(hipMemcpyAsync(hh.data(), d_h, sizeof(cxd) * ns * (R + 1), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(hh2.data(), d_h2, sizeof(cxd) * ns * (R + 1), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            precond_ms += ms;
-            if (h->prof_on) h->prof_collect();
-            ++total_its;
-            m_done = j + 1;
-            std::vector<int> conv, keep;
-            for (int q = 0; q < ns; ++q) {
-                ColState& C = cs[active[q]];
-                zd* Hc = &C.H[(size_t)j * (R + 1)];
-                for (int i = 0; i <= j; ++i) {
-                    const cxd a = hh[(size_t)q * (R + 1) + i], b = hh2[(size_t)q * (R + 1) + i];
-                    Hc[i] = zd(a.x + b.x, a.y + b.y);
+        if (h->opts.verbose > 0 && steps % h->opts.verbose == 0) {
+            double worst = 0.0;
+            int active = 0;
+            for (const auto& C : E.col)
+                if (C.phase == COL_ACTIVE) {
+                    worst = std::max(worst, C.est);
+                    ++active;
                 }
-                Hc[j + 1] = hn[q];
-                for (int i = 0; i < j; ++i) {
-                    const zd t = C.cs[i] * Hc[i] + C.sn[i] * Hc[i + 1];
-                    Hc[i + 1] = -std::conj(C.sn[i]) * Hc[i] + std::conj(C.cs[i]) * Hc[i + 1];
-                    Hc[i] = t;
-                }
-                const zd a = Hc[j], b = Hc[j + 1];
-                const double den = std::sqrt(std::norm(a) + std::norm(b));
-                C.cs[j] = den != 0.0 ? std::conj(a) / den : zd(1.0);
-                C.sn[j] = den != 0.0 ? std::conj(b) / den : zd(0.0);
-                Hc[j] = C.cs[j] * a + C.sn[j] * b;
-                Hc[j + 1] = 0.0;
-                C.g[j + 1] = -std::conj(C.sn[j]) * C.g[j];
-                C.g[j] = C.cs[j] * C.g[j];
-                C.its += 1;
-                C.est = std::abs(C.g[j + 1]) / C.bnorm;
-                const bool breakdown = hn[q] == 0.0;
-                if (std::abs(C.g[j + 1]) <= tol * C.bnorm || C.its >= h->max_outer || breakdown)
-                    conv.push_back(active[q]);
-                else
-                    keep.push_back(active[q]);
-            }
-            if (!conv.empty()) {
-                finish_cols(conv, j + 1);
-                for (int c : conv) cs[c].done = true;  // re-verified below
-            }
-            if (keep.empty()) break;
-            if (!conv.empty()) {
-                // compact: the device h/norm buffers are slot-indexed per call
-                active = keep;
-                HIPCHK(hipMemcpyAsync(d_cols, active.data(), sizeof(int) * active.size(),
-                                      hipMemcpyHostToDevice, s));
-            }
-            if (j == R - 1) {
-                finish_cols(active, R);  // restart the rest
-            }
-        }
-        (void)m_done;
-        // columns marked done are re-checked on the true residual
-        std::vector<int> chk;
-        for (int c = 0; c < nrhs; ++c)
-            if (cs[c].done) chk.push_back(c);
-        if (!chk.empty()) {
-            const int nc = (int)chk.size();
-            HIPCHK(hipMemcpyAsync(d_cols, chk.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
-            apply_B(MODE_RESID, cst(Xcol(d_cols)), Bcol(d_cols), Vcol(0, d_cols), nc);
-            norm2(s, N, cst(Vcol(0, d_cols)), d_npart, d_norm, 1, nc);
-            HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            for (int q = 0; q < nc; ++q) {
-                ColState& C = cs[chk[q]];
-                const double rel = C.bnorm > 0 ? hn[q] / C.bnorm : 0.0;
-                if (rel > tol && C.its < h->max_outer) C.done = false;  // restart it
-                C.est = rel;
-            }
+            fprintf(stderr, "[helm] step %d: max Arnoldi residual %.3e over %d active columns\n",
+                    steps, worst, active);
+            fflush(stderr);
         }
     }
-    HIPCHK(hipEventDestroy(e0));
-    HIPCHK(hipEventDestroy(e1));
-    // final true residuals
-    double worst = 0.0, worst_arn = 0.0;
-    int maxits = 0;
+    HIPCHK(hipMemcpyAsync(x, E.Xb(), sizeof(cxd) * N * nrhs, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->prof_on = false;
     bool ok = true;
-    {
-        HIPCHK(hipMemcpyAsync(d_cols, all.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-        apply_B(MODE_RESID, cst(Xcol(d_cols)), Bcol(d_cols), Vcol(0, d_cols), nrhs);
-        norm2(s, N, cst(Vcol(0, d_cols)), d_npart, d_norm, 1, nrhs);
-        HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int c = 0; c < nrhs; ++c) {
-            const double rel = cs[c].bnorm > 0 ? hn[c] / cs[c].bnorm : 0.0;
-            worst = std::max(worst, rel);
-            worst_arn = std::max(worst_arn, cs[c].est);
-            maxits = std::max(maxits, cs[c].its);
-            if (!(rel <= tol)) ok = false;
-        }
+    double worst = 0.0, worst_arn = 0.0;
+    int maxits = 0, restarts = 0;
+    for (const auto& C : E.col) {
+        ok = ok && C.converged;
+        worst = std::max(worst, C.true_rel);
+        worst_arn = std::max(worst_arn, C.est);
+        maxits = std::max(maxits, C.its);
+        restarts = std::max(restarts, C.restarts);
     }
     if (st) {
         st->outer_its = maxits;
         st->restarts = restarts;
         st->hss_steps = h->hss_steps;
-        st->vcycles = vcycles;
+        st->vcycles = E.vcycles;
         st->converged = ok ? 1 : 0;
         st->arnoldi_rel_residual = worst_arn;
         st->true_rel_residual = worst;
         st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        st->precond_ms = precond_ms;
+        st->precond_ms = E.precond_ms;
         st->sweep_ms = h->prof_ms;
         st->sweep_launches = h->prof_launches;
         st->sweep_bytes = h->prof_bytes;
         st->mg_cycles = h->cycles;
         st->vcycle_rate = h->vrate;
     }
-    h->prof_on = false;
-    (void)total_its;
     return ok ? HELM_OK : HELM_ENOCONV;
 }
 
@@ -936,6 +733,7 @@ void helm_opts_default(helm_opts* o) {
     o->mg_cycles = 0;
     o->no_graphs = 0;
     o->no_small = 0;
+    o->verbose = 0;
 }
 
 const char* helm_strerror(int status) {
@@ -1104,10 +902,10 @@ int helm_solve(helm_t* h, const void* rhs, void* x, int nrhs, double tol, void* 
     if (!(tol > 0.0 && tol < 1.0)) return HELM_EINVAL;
     try {
         if (h->prec == HELM_FP64)
-            return fgmres<double>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x), nrhs, tol,
-                                  workspace, stats);
-        return fgmres<float>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x), nrhs, tol,
-                             workspace, stats);
+            return solve_columns<double>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x),
+                                         nrhs, tol, workspace, stats);
+        return solve_columns<float>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x), nrhs,
+                                    tol, workspace, stats);
     } catch (const DevErr&) {
         return HELM_EDEVICE;
     } catch (const std::bad_alloc&) {
@@ -1325,3 +1123,6 @@ int helm_precondition(helm_t* h, const void* v, void* z, int nrhs, void* workspa
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ serving --
+#include "server_impl.h"

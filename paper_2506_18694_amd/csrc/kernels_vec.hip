@@ -104,8 +104,9 @@ __global__ __launch_bounds__(BS) void k_real_to_complex(long long N, const doubl
 
 // ---- Arnoldi reductions -------------------------------------------------------
 // part[(slot * m + i) * nblk + blk] = sum over the block's nodes of conj(V_i) w
-__global__ __launch_bounds__(BS) void k_multidot(long long N, int m, Vec<const cxd> V,
-                                                 Vec<const cxd> W, cxd* part, unsigned nblk) {
+__global__ __launch_bounds__(BS) void k_multidot(long long N, int m, const int* mlen,
+                                                 Vec<const cxd> V, Vec<const cxd> W, cxd* part,
+                                                 unsigned nblk) {
     __shared__ double lds[(BS / WAVE) * 2 * GROUP];
     const int slot = blockIdx.x / nblk;
     const unsigned blk = blockIdx.x % nblk;
@@ -118,13 +119,14 @@ __global__ __launch_bounds__(BS) void k_multidot(long long N, int m, Vec<const c
         long long t = base + (long long)q * BS;
         wv[q] = t < N ? w[t] : mk(0.0, 0.0);
     }
-    for (int i0 = 0; i0 < m; i0 += GROUP) {
+    const int ms = mlen ? mlen[slot] : m;  // this slot's vector count (<= m)
+    for (int i0 = 0; i0 < ms; i0 += GROUP) {
         double acc[2 * GROUP];
 #pragma unroll
         for (int c = 0; c < 2 * GROUP; ++c) acc[c] = 0.0;
 #pragma unroll
         for (int u = 0; u < GROUP; ++u) {
-            if (i0 + u < m) {
+            if (i0 + u < ms) {
                 const cxd* v = v0 + (long long)(i0 + u) * N;
 #pragma unroll
                 for (int q = 0; q < NPT; ++q) {
@@ -141,17 +143,19 @@ __global__ __launch_bounds__(BS) void k_multidot(long long N, int m, Vec<const c
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int u = 0; u < GROUP; ++u)
-                if (i0 + u < m)
+                if (i0 + u < ms)
                     part[((long long)slot * m + i0 + u) * nblk + blk] = mk(acc[2 * u], acc[2 * u + 1]);
         }
     }
 }
 
 // one block per (slot, i): out = sum over blocks, fixed order
-__global__ __launch_bounds__(BS) void k_reduce_parts(int m, int nblk, const cxd* part, cxd* out,
-                                                     int ostride, int accumulate) {
+__global__ __launch_bounds__(BS) void k_reduce_parts(int m, const int* mlen, int nblk,
+                                                     const cxd* part, cxd* out, int ostride,
+                                                     int accumulate) {
     __shared__ double lds[(BS / WAVE) * 2];
     const int slot = blockIdx.x / m, i = blockIdx.x % m;
+    if (mlen && i >= mlen[slot]) return;  // uniform over the block
     const cxd* p = part + ((long long)slot * m + i) * nblk;
     double acc[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < nblk; b += BS) {
@@ -197,35 +201,37 @@ __global__ __launch_bounds__(BS) void k_norm2_final(int nblk, const double* part
 }
 
 // w -= sum_i h_i V_i   (h from device memory, staged in LDS)
-__global__ __launch_bounds__(BS) void k_multi_axpy(long long N, int m, Vec<const cxd> V,
-                                                   const cxd* h, int hstride, Vec<cxd> W,
-                                                   unsigned gx) {
+__global__ __launch_bounds__(BS) void k_multi_axpy(long long N, int m, const int* mlen,
+                                                   Vec<const cxd> V, const cxd* h, int hstride,
+                                                   Vec<cxd> W, unsigned gx) {
     extern __shared__ cxd hs[];
     const int slot = blockIdx.x / gx;
-    for (int i = threadIdx.x; i < m; i += BS) hs[i] = h[(long long)slot * hstride + i];
+    const int ms = mlen ? mlen[slot] : m;
+    for (int i = threadIdx.x; i < ms; i += BS) hs[i] = h[(long long)slot * hstride + i];
     __syncthreads();
     const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
     if (t >= N) return;
     const cxd* v = V.at(slot);
     cxd acc = mk(0.0, 0.0);
-    for (int i = 0; i < m; ++i) acc = cfma(hs[i], v[(long long)i * N + t], acc);
+    for (int i = 0; i < ms; ++i) acc = cfma(hs[i], v[(long long)i * N + t], acc);
     cxd* w = W.at(slot);
     w[t] = w[t] - acc;
 }
 
 template <typename TZ>
-__global__ __launch_bounds__(BS) void k_update_solution(long long N, int m, Vec<const cx<TZ>> Z,
-                                                        const cxd* y, int ystride, Vec<cxd> X,
-                                                        unsigned gx) {
+__global__ __launch_bounds__(BS) void k_update_solution(long long N, int m, const int* mlen,
+                                                        Vec<const cx<TZ>> Z, const cxd* y,
+                                                        int ystride, Vec<cxd> X, unsigned gx) {
     extern __shared__ cxd ys[];
     const int slot = blockIdx.x / gx;
-    for (int i = threadIdx.x; i < m; i += BS) ys[i] = y[(long long)slot * ystride + i];
+    const int ms = mlen ? mlen[slot] : m;
+    for (int i = threadIdx.x; i < ms; i += BS) ys[i] = y[(long long)slot * ystride + i];
     __syncthreads();
     const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
     if (t >= N) return;
     const cx<TZ>* z = Z.at(slot);
     cxd acc = mk(0.0, 0.0);
-    for (int i = 0; i < m; ++i) acc = cfma(ys[i], cvt<double>(z[(long long)i * N + t]), acc);
+    for (int i = 0; i < ms; ++i) acc = cfma(ys[i], cvt<double>(z[(long long)i * N + t]), acc);
     cxd* x = X.at(slot);
     x[t] = x[t] + acc;
 }
@@ -266,21 +272,21 @@ void real_to_complex(hipStream_t st, long long N, const double* f, cxd* b, int n
     k_real_to_complex<<<gx * nslots, BS, 0, st>>>(N, f, b, gx);
 }
 
-void multidot(hipStream_t st, long long N, int m, Vec<const cxd> V, Vec<const cxd> W, cxd* part,
-              int nslots) {
+void multidot(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
+              Vec<const cxd> W, cxd* part, int nslots) {
     const unsigned nblk = multidot_blocks(N);
-    k_multidot<<<nblk * nslots, BS, 0, st>>>(N, m, V, W, part, nblk);
+    k_multidot<<<nblk * nslots, BS, 0, st>>>(N, m, mlen, V, W, part, nblk);
 }
 
-void reduce_parts(hipStream_t st, int m, int nblk, const cxd* part, cxd* out, int ostride,
-                  int accumulate, int nslots) {
-    k_reduce_parts<<<m * nslots, BS, 0, st>>>(m, nblk, part, out, ostride, accumulate);
+void reduce_parts(hipStream_t st, int m, const int* mlen, int nblk, const cxd* part, cxd* out,
+                  int ostride, int accumulate, int nslots) {
+    k_reduce_parts<<<m * nslots, BS, 0, st>>>(m, mlen, nblk, part, out, ostride, accumulate);
 }
 
-void multi_axpy(hipStream_t st, long long N, int m, Vec<const cxd> V, const cxd* h, int hstride,
-                Vec<cxd> W, int nslots) {
+void multi_axpy(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
+                const cxd* h, int hstride, Vec<cxd> W, int nslots) {
     const unsigned gx = blocks(N);
-    k_multi_axpy<<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, V, h, hstride, W, gx);
+    k_multi_axpy<<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, mlen, V, h, hstride, W, gx);
 }
 
 void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* out, int ostride,
@@ -291,10 +297,11 @@ void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* 
 }
 
 template <typename TZ>
-void update_solution(hipStream_t st, long long N, int m, Vec<const cx<TZ>> Z, const cxd* y,
-                     int ystride, Vec<cxd> X, int nslots) {
+void update_solution(hipStream_t st, long long N, int m, const int* mlen, Vec<const cx<TZ>> Z,
+                     const cxd* y, int ystride, Vec<cxd> X, int nslots) {
     const unsigned gx = blocks(N);
-    k_update_solution<TZ><<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, Z, y, ystride, X, gx);
+    k_update_solution<TZ><<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, mlen, Z, y, ystride, X,
+                                                                     gx);
 }
 
 template void coarse_apply<double>(hipStream_t, const cxd*, int, Vec<const cxd>, Vec<cxd>, int);
@@ -305,9 +312,9 @@ template void copy_cast<double, float>(hipStream_t, long long, Vec<const cxf>, V
 template void copy_cast<float, float>(hipStream_t, long long, Vec<const cxf>, Vec<cxf>, int);
 template void axpy1<double>(hipStream_t, long long, double, Vec<const cxd>, Vec<cxd>, int);
 template void axpy1<float>(hipStream_t, long long, float, Vec<const cxf>, Vec<cxf>, int);
-template void update_solution<double>(hipStream_t, long long, int, Vec<const cxd>, const cxd*,
-                                      int, Vec<cxd>, int);
-template void update_solution<float>(hipStream_t, long long, int, Vec<const cxf>, const cxd*,
-                                     int, Vec<cxd>, int);
+template void update_solution<double>(hipStream_t, long long, int, const int*, Vec<const cxd>,
+                                      const cxd*, int, Vec<cxd>, int);
+template void update_solution<float>(hipStream_t, long long, int, const int*, Vec<const cxf>,
+                                     const cxd*, int, Vec<cxd>, int);
 
 }  // namespace helm

@@ -90,21 +90,22 @@ void scale_inv(hipStream_t st, long long N, Vec<const cxd> X, Vec<cxd> Y, const 
 // partial dot products: part[slot][i][blk] = sum_{n in blk} conj(V_i[n]) w[n], i < m
 // V_i at Vb.at(slot) + i*N
 int multidot_blocks(long long N);
-void multidot(hipStream_t st, long long N, int m, Vec<const cxd> V, Vec<const cxd> W, cxd* part,
-              int nslots);
+// mlen (nullable, device): per-slot vector count <= m; m sets the layout
+void multidot(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
+              Vec<const cxd> W, cxd* part, int nslots);
 // reduce part over blocks: out[slot*ostride + i] (+)= sum_blk part[slot][i][blk]
-void reduce_parts(hipStream_t st, int m, int nblk, const cxd* part, cxd* out, int ostride,
-                  int accumulate, int nslots);
+void reduce_parts(hipStream_t st, int m, const int* mlen, int nblk, const cxd* part, cxd* out,
+                  int ostride, int accumulate, int nslots);
 // w -= sum_{i<m} h[slot*hstride + i] V_i
-void multi_axpy(hipStream_t st, long long N, int m, Vec<const cxd> V, const cxd* h, int hstride,
-                Vec<cxd> W, int nslots);
+void multi_axpy(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
+                const cxd* h, int hstride, Vec<cxd> W, int nslots);
 // squared norm partials: part[slot][blk] = sum |w|^2 ; reduced into out[slot*ostride]
 void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* out, int ostride,
            int nslots);
 // x += sum_{i<m} y[slot*ystride + i] Z_i  (Z in FP64 or FP32)
 template <typename TZ>
-void update_solution(hipStream_t st, long long N, int m, Vec<const cx<TZ>> Z, const cxd* y,
-                     int ystride, Vec<cxd> X, int nslots);
+void update_solution(hipStream_t st, long long N, int m, const int* mlen, Vec<const cx<TZ>> Z,
+                     const cxd* y, int ystride, Vec<cxd> X, int nslots);
 // b = f (real -> complex)
 void real_to_complex(hipStream_t st, long long N, const double* f, cxd* b, int nslots);
 

@@ -22,7 +22,9 @@ OPS = {"B0": 0, "BDELTA": 1, "BSHIFT": 2, "L": 3, "N": 4, "H": 5, "M": 6}
 EXPORTS = ("helm_opts_default", "helm_strerror", "helm_create", "helm_destroy", "helm_nodes",
            "helm_workspace_bytes", "helm_solve", "helm_load_nodal", "helm_apply",
            "helm_hss_residual", "helm_jacobi", "helm_restrict_residual", "helm_prolong_correct",
-           "helm_coarse_solve", "helm_vcycle", "helm_precondition", "helm_last_error")
+           "helm_coarse_solve", "helm_vcycle", "helm_precondition", "helm_last_error",
+           "helm_server_create", "helm_server_submit", "helm_server_step", "helm_server_query",
+           "helm_server_load", "helm_server_destroy")
 
 
 class HelmError(RuntimeError):
@@ -49,7 +51,8 @@ class helm_opts(ctypes.Structure):
                 ("omega", ctypes.c_double), ("hss_m", ctypes.c_int), ("hss_steps", ctypes.c_int),
                 ("restart", ctypes.c_int), ("max_outer", ctypes.c_int), ("x0_given", ctypes.c_int),
                 ("profile", ctypes.c_int), ("mg_cycles", ctypes.c_int),
-                ("no_graphs", ctypes.c_int), ("no_small", ctypes.c_int)]
+                ("no_graphs", ctypes.c_int), ("no_small", ctypes.c_int),
+                ("verbose", ctypes.c_int)]
 
 
 class helm_stats(ctypes.Structure):
@@ -60,6 +63,21 @@ class helm_stats(ctypes.Structure):
                 ("precond_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double),
                 ("sweep_launches", ctypes.c_longlong), ("sweep_bytes", ctypes.c_double),
                 ("mg_cycles", ctypes.c_int), ("vcycle_rate", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class helm_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_double), ("max_cols", ctypes.c_int),
+                ("precision", ctypes.c_int), ("restart", ctypes.c_int),
+                ("max_outer", ctypes.c_int)]
+
+
+class helm_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("converged", ctypes.c_int), ("outer_its", ctypes.c_int),
+                ("true_rel_residual", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -97,6 +115,12 @@ def lib():
         "helm_coarse_solve": (I, [P, I, P, P, I]),
         "helm_vcycle": (I, [P, I, P, P, I, P]),
         "helm_precondition": (I, [P, P, P, I, P]),
+        "helm_server_create": (I, [ctypes.POINTER(helm_server_opts), ctypes.POINTER(P)]),
+        "helm_server_submit": (I, [P, I, I, I, D, D, P, P, I, D, ctypes.POINTER(ctypes.c_longlong)]),
+        "helm_server_step": (I, [P, ctypes.POINTER(I)]),
+        "helm_server_query": (I, [P, ctypes.c_longlong, ctypes.POINTER(helm_request_info)]),
+        "helm_server_load": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "helm_server_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -137,7 +161,7 @@ class Solver:
     def __init__(self, dim, n, levels, k, delta=0.0, delta_hat=None, precision="fp64",
                  restart=0, max_outer=0, hss_steps=0, hss_m=1, omega=2.0 / 3.0,
                  dirichlet_faces=0, profile=False, mg_cycles=0, graphs=True, small_kernel=True,
-                 stream=None):
+                 verbose=0, stream=None):
         import torch
         self.torch = torch
         L = lib()
@@ -151,6 +175,7 @@ class Solver:
         opts.mg_cycles = mg_cycles
         opts.no_graphs = 0 if graphs else 1
         opts.no_small = 0 if small_kernel else 1
+        opts.verbose = int(verbose)
         bc = helm_bc(dirichlet_faces)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -311,3 +336,63 @@ class Solver:
         _check(lib().helm_precondition(self.h, _ptr(v), _ptr(z), nrhs,
                                        _ptr(self.workspace(nrhs))), "helm_precondition")
         return z
+
+
+class Server:
+    """helm_server_t: continuous batching of independent solves (marshalling
+    only; admission, batching and the solves run in libhelm)."""
+
+    def __init__(self, hbm_budget_bytes, max_cols=8, precision="fp32", restart=0, max_outer=0):
+        import torch
+        self.torch = torch
+        o = helm_server_opts(float(hbm_budget_bytes), int(max_cols),
+                             HELM_FP64 if precision == "fp64" else HELM_FP32_MG,
+                             int(restart), int(max_outer))
+        handle = ctypes.c_void_p()
+        _check(lib().helm_server_create(ctypes.byref(o), ctypes.byref(handle)), "helm_server_create")
+        self.s = handle
+        self._keep = {}  # request id -> (rhs, x) tensors kept alive until done
+
+    def submit(self, rhs, n, levels, k, delta_hat=None, dim=2, tol=1e-8):
+        """Queue rhs (complex128 CUDA tensor, (nrhs, N)); returns (id, x)."""
+        if rhs.dtype != self.torch.complex128 or rhs.device.type != "cuda" or not rhs.is_contiguous():
+            raise ValueError("rhs must be a contiguous complex128 CUDA tensor")
+        rhs2 = rhs if rhs.dim() == 2 else rhs[None]
+        x = self.torch.empty_like(rhs2)
+        rid = ctypes.c_longlong()
+        dh = float(k) if delta_hat is None else float(delta_hat)
+        _check(lib().helm_server_submit(self.s, dim, n, levels, float(k), dh, _ptr(rhs2), _ptr(x),
+                                        rhs2.shape[0], float(tol), ctypes.byref(rid)),
+               "helm_server_submit")
+        self._keep[rid.value] = (rhs2, x)
+        return rid.value, x
+
+    def step(self):
+        done = ctypes.c_int()
+        _check(lib().helm_server_step(self.s, ctypes.byref(done)), "helm_server_step")
+        return done.value
+
+    def query(self, rid):
+        info = helm_request_info()
+        _check(lib().helm_server_query(self.s, rid, ctypes.byref(info)), "helm_server_query")
+        d = info.as_dict()
+        if d["status"] == 2:
+            self._keep.pop(rid, None)
+        return d
+
+    def load(self):
+        q, r, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().helm_server_load(self.s, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)),
+               "helm_server_load")
+        return q.value, r.value, b.value
+
+    def close(self):
+        if getattr(self, "s", None):
+            lib().helm_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

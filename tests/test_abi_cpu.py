@@ -85,3 +85,24 @@ def test_null_handle_calls_are_rejected():
     assert L.helm_apply(None, 0, 0, 0, None, None, 1) == helm.HELM_EINVAL
     assert L.helm_vcycle(None, 0, None, None, 1, None) == helm.HELM_EINVAL
     assert L.helm_precondition(None, None, None, 1, None) == helm.HELM_EINVAL
+
+
+def test_server_rejects_invalid_options():
+    helm, L = _lib()
+    out = ctypes.c_void_p(1)
+    for o in (helm.helm_server_opts(0.0, 4, 1, 0, 0), helm.helm_server_opts(1e9, 0, 1, 0, 0),
+              helm.helm_server_opts(1e9, 4, 7, 0, 0), helm.helm_server_opts(1e9, 4, 1, -1, 0)):
+        assert L.helm_server_create(ctypes.byref(o), ctypes.byref(out)) == helm.HELM_EINVAL
+    assert L.helm_server_create(None, ctypes.byref(out)) == helm.HELM_EINVAL
+    ok = helm.helm_server_opts(1e9, 4, 1, 0, 0)
+    assert L.helm_server_create(ctypes.byref(ok), ctypes.byref(out)) == helm.HELM_OK
+    rid = ctypes.c_longlong()
+    dummy = ctypes.c_void_p(16)
+    # nrhs above max_cols, bad mesh, bad tol: rejected before any device work
+    assert L.helm_server_submit(out, 2, 64, 4, 6.4, 6.4, dummy, dummy, 5, 1e-8, ctypes.byref(rid)) == helm.HELM_EINVAL
+    assert L.helm_server_submit(out, 2, 60, 4, 6.4, 6.4, dummy, dummy, 1, 1e-8, ctypes.byref(rid)) == helm.HELM_EINVAL
+    assert L.helm_server_submit(out, 2, 64, 4, 6.4, 6.4, dummy, dummy, 1, 2.0, ctypes.byref(rid)) == helm.HELM_EINVAL
+    q, r, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    assert L.helm_server_load(out, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)) == helm.HELM_OK
+    assert (q.value, r.value, b.value) == (0, 0, 0.0)
+    assert L.helm_server_destroy(out) == helm.HELM_OK

@@ -91,3 +91,25 @@ def random_complex(shape, seed):
     """Standard complex normal array (real and imaginary parts N(0, 1))."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def serving_stream(count, sizes=(128, 256, 512, 1024), max_rhs=8, rate=None, seed=1,
+                   coarsest=8):
+    """Seeded request stream for the serving workload: mesh size n uniform
+    over `sizes`, k = n/10, delta_hat = k, 1..max_rhs right-hand sides, each
+    a Gaussian of sigma 2/n at a uniform centre, Poisson arrivals with the
+    given rate (requests per second; None = all at t = 0).  Levels are chosen
+    so the coarsest mesh has `coarsest` cells per side."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for i in range(count):
+        n = int(rng.choice(np.asarray(sizes)))
+        nrhs = int(rng.integers(1, max_rhs + 1))
+        centres = rng.uniform(0.0, 1.0, size=(nrhs, 2))
+        if rate:
+            t += float(rng.exponential(1.0 / rate))
+        levels = int(round(np.log2(n / coarsest))) + 1
+        out.append(dict(id=i, n=n, k=n / 10.0, levels=levels, nrhs=nrhs, centres=centres,
+                        sigma=2.0 / n, arrival=t))
+    return out
