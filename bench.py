@@ -113,6 +113,69 @@ def cpu_baseline(W, name, outer_its, cycles, sample_steps):
                                   pr.hss_steps(), nrhs)}
 
 
+def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1):
+    """Continuous-batching run: requests arrive by a seeded Poisson process
+    and are submitted when their arrival time passes; the server steps
+    continuously.  Latency = completion - arrival (wall clock)."""
+    import numpy as np
+    import torch
+    from paper_2506_18694_amd import Server, Solver
+    reqs = W.serving_stream(count, sizes=sizes, max_rhs=8, rate=rate, seed=seed)
+    # load vectors b = M f on the device (set-up, untimed)
+    loaders = {}
+    rhs = []
+    for r in reqs:
+        n = r["n"]
+        if n not in loaders:
+            loaders[n] = Solver(2, n, r["levels"], r["k"], 0.0, r["k"], precision=precision)
+        f = np.stack([W.gaussian_nodal(2, n, c, r["sigma"]) for c in r["centres"]])
+        rhs.append(loaders[n].load_nodal(torch.from_numpy(f).cuda()))
+    torch.cuda.synchronize()
+    for s in loaders.values():
+        s.close()
+    srv = Server(hbm_budget_bytes=budget_gb * 1e9, max_cols=max_cols, precision=precision)
+    ids, lat, its, conv = {}, {}, [], []
+    t0 = time.perf_counter()
+    nxt = 0
+    done = 0
+    dof = 0
+    while done < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt]["arrival"] <= now:
+            r = reqs[nxt]
+            ids[nxt], _ = srv.submit(rhs[nxt], r["n"], r["levels"], r["k"], tol=1e-8)
+            nxt += 1
+        if not ids:
+            time.sleep(max(0.0, reqs[nxt]["arrival"] - now))
+            continue
+        srv.step()
+        t = time.perf_counter() - t0
+        for i, rid in ids.items():
+            if i in lat:
+                continue
+            info = srv.query(rid)
+            if info["status"] == 2:
+                lat[i] = t - reqs[i]["arrival"]
+                its.append(info["outer_its"])
+                conv.append(info["converged"])
+                dof += (reqs[i]["n"] + 1) ** 2 * reqs[i]["nrhs"]
+                done += 1
+                if done % 8 == 0:
+                    q, run, used = srv.load()
+                    log("[serving] %d/%d done at %.1f s, queued %d running %d, %.1f GB in use"
+                        % (done, len(reqs), t, q, run, used / 1e9))
+        if nxt == len(reqs) and not ids:
+            break
+    makespan = time.perf_counter() - t0
+    srv.close()
+    L = np.array([lat[i] for i in range(len(reqs))])
+    return {"requests": len(reqs), "sizes": list(sizes), "rate_per_s": rate, "max_cols": max_cols,
+            "precision": precision, "p50_latency_s": float(np.percentile(L, 50)),
+            "p99_latency_s": float(np.percentile(L, 99)), "mean_latency_s": float(L.mean()),
+            "makespan_s": makespan, "dofs_per_s": dof / makespan,
+            "mean_outer_its": float(np.mean(its)), "all_converged": bool(all(conv))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +188,13 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: 3 outer iterations, no extras")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the continuous-batching serving workload instead (one JSON line)")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--sizes", default="128,256,512")
+    ap.add_argument("--rate", type=float, default=8.0)
+    ap.add_argument("--max-cols", type=int, default=16)
+    ap.add_argument("--budget-gb", type=float, default=120.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X and "
@@ -136,6 +206,19 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.serving:
+        sizes = tuple(int(v) for v in args.sizes.split(","))
+        res = run_serving(W, args.requests, sizes, args.rate, args.max_cols, args.budget_gb, "fp32")
+        out = {"metric": "serving p50/p99 latency (continuous batching, FP32-MG/FP64-outer)",
+               "value": res["p99_latency_s"], "unit": "s (p99)", "n_gpus": 1, "steps": 1,
+               "warmup": 0, "ms_per_step": res["makespan_s"] * 1e3, "higher_is_better": False,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+               "config": {"workload": "serving-2d-p1", **{k: v for k, v in res.items()
+                                                          if k in ("requests", "sizes", "rate_per_s",
+                                                                   "max_cols", "precision")}},
+               "serving": res}
+        print(json.dumps(out), flush=True)
+        return
     name = args.workload
     prec = W.WORKLOADS[name]["precision"]
     main_prec = "fp64" if prec == "fp64" else "fp32"

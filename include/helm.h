@@ -108,10 +108,11 @@ typedef struct {
                           starts from the previous iterate).  0 = automatic:
                           with exact inner solves the HSS error contracts by
                           (k-1)/(k+1) per step (Sec. 3.1 proposition); an
-                          inexact solve keeps that only while its error is
-                          below the gap 2/(k+1), so the library measures the
-                          V-cycle rate rho_V once (power iteration) and uses
-                          the smallest q >= 2 with rho_V^q <= 2/(k+1).       */
+                          inexact solve with error E changes the step's map T
+                          to T + E (I - T), still a contraction when
+                          |E| < (1 - nu)/(1 + nu) = 1/k; the library measures
+                          the V-cycle rate rho_V once (power iteration) and
+                          uses the smallest q >= 2 with rho_V^q <= 1/k.      */
     int    no_graphs;  /* 1: launch the preconditioner's kernels one by one;
                           default 0 replays one captured HIP graph of the
                           whole HSS loop per application (captured on a

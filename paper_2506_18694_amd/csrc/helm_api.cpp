@@ -7,7 +7,8 @@
 // (Definition "Shifted HSS iteration for the primal system") in correction
 // form
 //     u_{s+1} = u_s + V( (2k/(k+1)) (R - B_dh u_s) ),   u_0 = 0,
-// s = 0 .. m ceil(k) - 1, where V is one V(2,2) cycle for
+// s = 0 .. m ceil(k) - 1, where V is q V(2,2) cycles (each after the first
+// starting from the previous result) for
 //     L = K + (dh^2 - k^2 - 2i dh k^2) M + (dh - i k^2) M_Gamma
 // (the left-hand side of eq. (HSSpc primal)); with exact inner solves this
 // equals the literal two-term form of the definition.  The cycle uses
@@ -525,11 +526,11 @@ void hss_loop(helm_t* h, const Layout& Lw, void* ws, int ns) {
 // Number of V-cycles per inner HSS solve.  With exact inner solves the HSS
 // error contracts by nu = (k-1)/(k+1) per step in the H-norm (the Cayley
 // transform is H-unitary).  An inexact inner solve with cycle error E turns
-// the step's error map T into T + E(I - T); its contraction survives only if
-// the cycle error stays below the gap 1 - nu = 2/(k+1).  The V-cycle rate
-// rho_V is measured once per handle by power iteration on the cycle's error
-// map e <- e - V(L e) from a fixed pseudo-random start, and the smallest q
-// with rho_V^q <= 2/(k+1) is used (at least 2, at most 8).
+// the step's error map T into T + E(I - T); as ||I - T|| <= 1 + nu, it stays
+// a contraction when ||E|| (1 + nu) < 1 - nu, i.e. ||E|| < 1/k.  The V-cycle
+// rate rho_V is measured once per handle by power iteration on the cycle's
+// error map e <- e - V(L e) from a fixed pseudo-random start, and the
+// smallest q with rho_V^q <= 1/k is used (at least 2, at most 8).
 template <typename T>
 void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
     if (!h->cycles_auto || h->vrate > 0.0) return;
@@ -570,9 +571,10 @@ void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
     double rate = std::pow(norms[iters - 1] / norms[iters - 4], 1.0 / 3.0);
     if (!(rate > 0.0) || !std::isfinite(rate)) rate = 0.5;
     h->vrate = rate;
-    const double gap = 2.0 / (h->k + 1.0);
+    // ||T + E (I - T)|| <= nu + rho^q (1 + nu) < 1  <=>  rho^q < (1 - nu)/(1 + nu) = 1/k
+    const double bound = 1.0 / h->k;
     int q = 2;
-    while (q < 8 && std::pow(rate, q) > gap) ++q;
+    while (q < 8 && std::pow(rate, q) > bound) ++q;
     h->cycles = q;
 }
 
