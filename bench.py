@@ -34,9 +34,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the dominant kernel: finest-level prolongation, four Jacobi sweeps (cycle
+# q's post-smoothing and cycle q+1's pre-smoothing) and the residual
+# restriction in one register-streaming pass
+DOMINANT = {"tag": "k_stream_sweeps4", "source": "kernels2d_stream.hip",
+            "desc": "finest-level prolongation + four Jacobi sweeps + residual restriction "
+                    "(k_stream_sweeps<S=4>)"}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels2d_fused.hip", "helm_common.h", "stencil_rows.h"):
+    for f in (DOMINANT["source"], "helm_common.h", "stencil_rows.h"):
         with open(os.path.join(ROOT, "paper_2506_18694_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -45,7 +53,7 @@ def kernel_source_hash():
 def stored_traffic(workload, precision):
     """HBM traffic per launch of the dominant kernel from committed rocprofv3
     counter runs; null when the kernel source changed since they were taken."""
-    path = os.path.join(PROFILES, "traffic_k_sweeps4_%s_%s.json" % (workload, precision))
+    path = os.path.join(PROFILES, "traffic_%s_%s_%s.json" % (DOMINANT["tag"], workload, precision))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -55,13 +63,13 @@ def stored_traffic(workload, precision):
     return rec.get("bytes_per_launch")
 
 
-def run_solves(W, name, precision, steps, warmup, tol, max_outer=0):
+def run_solves(W, name, precision, steps, warmup, tol, max_outer=0, streaming=True):
     import torch
     from paper_2506_18694_amd import Solver
     w = W.WORKLOADS[name]
     s = Solver(w["dim"], w["n"], w["levels"], w["k"], w["delta"], w["delta_hat"],
                precision=precision, profile=True, max_outer=max_outer,
-               restart=max_outer if max_outer else 0)
+               restart=max_outer if max_outer else 0, streaming=streaming)
     f = torch.from_numpy(W.workload_sources(name)).cuda().contiguous()
     b = s.load_nodal(f)
     x = torch.empty_like(b)
@@ -184,6 +192,9 @@ def main():
     ap.add_argument("--workload", default="p1-1024-k100")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--lds-kernels", action="store_true",
+                    help="run the large 2D levels with the LDS-tiled kernels instead of the "
+                         "register-streaming ones (for comparison)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--profile-run", action="store_true",
@@ -225,7 +236,7 @@ def main():
     if args.profile_run:
         args.no_fp32 = args.no_cpu_baseline = True
     r = run_solves(W, name, main_prec, args.steps, args.warmup, args.tol,
-                   max_outer=3 if args.profile_run else 0)
+                   max_outer=3 if args.profile_run else 0, streaming=not args.lds_kernels)
     ms = r["elapsed"] / args.steps * 1e3
     value = r["N"] * r["nrhs"] / (ms / 1e3)
     sw_ms = sum(st["sweep_ms"] for st in r["stats"])
@@ -236,7 +247,7 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": stored_traffic(name, main_prec),
-            "kernel": "finest-level prolongation + four Jacobi sweeps (k_sweeps<S=4>)",
+            "kernel": DOMINANT["desc"],
             "bytes_per_launch": per_launch,
             "avg_launch_us": sw_ms / sw_n * 1e3 if sw_n else None}
     w = r["w"]
@@ -256,7 +267,7 @@ def main():
                       "converged": r["ok"]},
            "roofline": roof}
     if not args.no_fp32 and main_prec == "fp64":
-        r32 = run_solves(W, name, "fp32", 1, 1, args.tol)
+        r32 = run_solves(W, name, "fp32", 1, 1, args.tol, streaming=not args.lds_kernels)
         ms32 = r32["elapsed"] * 1e3
         v32 = r32["N"] * r32["nrhs"] / (ms32 / 1e3)
         s32 = r32["stats"][0]

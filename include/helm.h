@@ -123,6 +123,11 @@ typedef struct {
                           coarsest run as one LDS-resident kernel per cycle  */
     int    verbose;    /* > 0: print the Arnoldi residual estimate to stderr
                           every `verbose` outer iterations                   */
+    int    no_stream;  /* 1: run the large 2D levels with the LDS-tiled
+                          kernels; by default they run with the register-
+                          streaming kernels (one wavefront marches up a
+                          strip of 64 columns, every sweep a pipeline stage
+                          one row behind the previous one)                   */
 } helm_opts;
 
 typedef struct {

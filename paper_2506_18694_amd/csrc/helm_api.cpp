@@ -98,6 +98,10 @@ Op2<T> make_op2(const Coef& cf, int n, double omega) {
     o.odE = tocx<T>(omega / (2.0 * A + 6.0 * Bm + 4.0 * Cg));
     o.odA = tocx<T>(omega / (A + 4.0 * Bm + 4.0 * Cg));
     o.odB = tocx<T>(omega / (A + 2.0 * Bm + 4.0 * Cg));
+    // row of a boundary-column node (0, j) or (n, j), 0 < j < n: centre and
+    // north/south weights (the other weights are the interior ones)
+    o.wCe = tocx<T>(2.0 * A + 6.0 * Bm + 4.0 * Cg);
+    o.wNe = tocx<T>(-0.5 * A + Bm + Cg);
     o.omega = (T)omega;
     o.n = n;
     return o;
@@ -412,6 +416,12 @@ void run_small(helm_t* h, int l0, Vec<const cx<T>> b, Vec<cx<T>> x, int ns) {
     vcycle_small<T>(h->stream, sc, sizeof(cx<T>) * (size_t)off, h->d_cinv, h->nc, b, x, ns);
 }
 
+// Levels that run with the register-streaming kernels: every 2D level
+// above the small-level kernel, unless switched off.
+inline bool use_stream(const helm_t* h, int l) {
+    return h->dim == 2 && !h->opts.no_stream && h->nl[l] >= 16;
+}
+
 // Fused 2D cycle from a zero initial guess on level l (l >= 1 inside the HSS
 // loop, or l = 0 for a stand-alone cycle).  b is read, x and t are this
 // level's work buffers; returns the buffer holding the result (x or t).
@@ -434,6 +444,13 @@ Vec<cx<T>> vcycle2d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const
     Vec<cx<T>> bc = at_ws<cx<T>>(ws, Lw.mg_b[l + 1], Nc);
     Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
     Vec<cx<T>> tc = at_ws<cx<T>>(ws, Lw.mg_t[l + 1], Nc);
+    if (use_stream(h, l)) {
+        stream_pre_2d<T>(h->stream, L, L, (T)0, Vec<const cx<T>>{}, Vec<const cx<T>>{},
+                         Vec<cx<T>>{}, b, x, bc, ns);
+        Vec<cx<T>> ec = vcycle2d_zero<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
+        stream_sweeps_2d<T>(h->stream, L, 2, cst(x), cst(ec), b, t, Vec<cx<T>>{}, false, ns);
+        return t;
+    }
     pre0r_2d<T>(h->stream, L, b, x, bc, ns);
     Vec<cx<T>> ec = vcycle2d_zero<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
     sweeps_2d<T>(h->stream, L, 2, cst(x), cst(ec), b, t, false, ns);
@@ -471,6 +488,36 @@ void hss_loop2d(helm_t* h, const Layout& Lw, void* ws, int ns) {
     Vec<cx<T>> b1 = at_ws<cx<T>>(ws, Lw.mg_b[1], N1);
     Vec<cx<T>> x1 = at_ws<cx<T>>(ws, Lw.mg_x[1], N1);
     Vec<cx<T>> t1 = at_ws<cx<T>>(ws, Lw.mg_t[1], N1);
+    if (use_stream(h, 0)) {
+        // register-streaming kernels: cycle q's post-smoothing, cycle q+1's
+        // pre-smoothing and its residual restriction form one pass
+        for (int s = 0; s < h->hss_steps; ++s) {
+            Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
+            stream_pre_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, Vec<const cx<T>>{}, xa, b1, ns);
+            Vec<cx<T>> x = xa, t = xb;
+            for (int q = 0; q < h->cycles; ++q) {
+                Vec<const cx<T>> ec = cst(vcycle2d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
+                const bool last = q == h->cycles - 1;
+                const bool prof = h->prof_on && (h->cycles == 1 || !last);
+                if (prof) h->prof_mark();
+                if (last) {
+                    stream_sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, Vec<cx<T>>{}, true,
+                                        ns);
+                } else {
+                    stream_sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, b1, false, ns);
+                    std::swap(x, t);
+                }
+                if (prof) {
+                    h->prof_mark();
+                    // algorithmic bytes: x, b and e_c (a quarter vector) read,
+                    // x' and b_c (a quarter vector) written; the update pass
+                    // reads u and writes it instead of x' and b_c
+                    h->prof_pending_bytes += sizeof(cx<T>) * (double)N * ns * (last ? 4.25 : 3.5);
+                }
+            }
+        }
+        return;
+    }
     for (int s = 0; s < h->hss_steps; ++s) {
         Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
         hss_pre0r_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, xa, b1, ns);
@@ -736,6 +783,7 @@ void helm_opts_default(helm_opts* o) {
     o->no_graphs = 0;
     o->no_small = 0;
     o->verbose = 0;
+    o->no_stream = 0;
 }
 
 const char* helm_strerror(int status) {

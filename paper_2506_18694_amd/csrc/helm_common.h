@@ -81,11 +81,15 @@ inline Vec<V> contiguous(V* p, long long n) { return Vec<V>{p, n, 0, nullptr}; }
 // corner types of the right-diagonal mesh ((0,0)/(n,n) touch two triangles,
 // (n,0)/(0,n) one), so the Jacobi factors omega / D are precomputed:
 // odC interior, odE edge, odA corners (0,0)/(n,n), odB corners (n,0)/(0,n).
+// On the mesh columns i = 0 and i = n (away from the corners) the element
+// row has centre weight wCe, north and south weights wNe, wAx towards the
+// one horizontal neighbour and wDg towards the one diagonal neighbour.
 template <typename T>
 struct Op2 {
     cx<T> A, Bm, Cg;
     cx<T> wC, wAx, wDg;
     cx<T> odC, odE, odA, odB;
+    cx<T> wCe, wNe;
     T omega;
     int n;
 };

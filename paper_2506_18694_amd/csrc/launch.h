@@ -48,6 +48,30 @@ template <typename T>
 void hss_pre0r_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<const cx<T>> U,
                   Vec<const cx<T>> R, Vec<cx<T>> Rho, Vec<cx<T>> X, Vec<cx<T>> Bc, int ns);
 
+// ---- register-streaming 2D kernels (kernels2d_stream.hip) -----------------
+// Work split: strips of 64 columns (one per lane) x segments of H rows x
+// slots; one wavefront per unit.
+struct StreamGrid {
+    int H;
+    unsigned strips, segs, units;
+};
+StreamGrid stream_grid(int n, int halo, int ns, int H);
+// x_out = S Jacobi sweeps from x_in (+ P e_c when Ec.base is set); with
+// update, x_out += result; when Bc.base is set, also b_c = P^T (b - L x_out)
+// on the n/2 mesh.  Supported: (S, prolong, restrict, update) in
+// {(4,1,1,0), (2,1,0,1), (2,1,0,0), (2,0,1,0), (4,1,0,0), (1,0,0,0)}.
+template <typename T>
+void stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin,
+                      Vec<const cx<T>> Ec, Vec<const cx<T>> B, Vec<cx<T>> Xout, Vec<cx<T>> Bc,
+                      bool update, int ns);
+// two zero-guess pre-smoothing sweeps x for L x = b and b_c = P^T (b - L x);
+// b given (B.base set), or b = rho = c (R - B_shift u) (U.base set) or
+// rho = c R (neither), rho then written.
+template <typename T>
+void stream_pre_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<const cx<T>> U,
+                   Vec<const cx<T>> R, Vec<cx<T>> Rho, Vec<const cx<T>> B, Vec<cx<T>> X,
+                   Vec<cx<T>> Bc, int ns);
+
 // ---- small-level V-cycle in LDS (kernels2d_small.hip) ---------------------
 // Levels 0..nlev-1 of this record are consecutive mesh levels; the last is
 // the coarsest (solved with the dense FP64 inverse).  Offsets are in
