@@ -128,6 +128,11 @@ typedef struct {
                           streaming kernels (one wavefront marches up a
                           strip of 64 columns, every sweep a pipeline stage
                           one row behind the previous one)                   */
+    int    no_split;   /* 1: run the preconditioner of all columns as one
+                          batch; by default, with two or more columns, the
+                          columns are split into two groups whose HSS loops
+                          run on two streams, so that one group's finest-
+                          level passes overlap the other's coarse levels    */
 } helm_opts;
 
 typedef struct {

@@ -98,10 +98,13 @@ Op2<T> make_op2(const Coef& cf, int n, double omega) {
     o.odE = tocx<T>(omega / (2.0 * A + 6.0 * Bm + 4.0 * Cg));
     o.odA = tocx<T>(omega / (A + 4.0 * Bm + 4.0 * Cg));
     o.odB = tocx<T>(omega / (A + 2.0 * Bm + 4.0 * Cg));
-    // row of a boundary-column node (0, j) or (n, j), 0 < j < n: centre and
-    // north/south weights (the other weights are the interior ones)
-    o.wCe = tocx<T>(2.0 * A + 6.0 * Bm + 4.0 * Cg);
-    o.wNe = tocx<T>(-0.5 * A + Bm + Cg);
+    // boundary corrections of the interior stencil (zero values outside):
+    // edge centre and along-edge weights minus the interior ones, and the
+    // corners' remaining centre terms
+    o.dC = tocx<T>(-2.0 * A - 6.0 * Bm + 4.0 * Cg);
+    o.dN = tocx<T>(0.5 * A - Bm + Cg);
+    o.kA = tocx<T>(A + 4.0 * Bm - 4.0 * Cg);
+    o.kB = tocx<T>(A + 2.0 * Bm - 4.0 * Cg);
     o.omega = (T)omega;
     o.n = n;
     return o;
@@ -198,11 +201,14 @@ struct helm_s {
     // slot count, precision and cycle count; captured on cap_stream
     struct GraphEntry {
         void* ws;
-        int ns, tag, cycles;
+        int s0, ns, tag, cycles;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
+    // second stream (and fork/join events) for the second group of slots
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     // optional HIP-event timing of the finest-level Jacobi sweeps
     bool prof_on = false;
@@ -457,13 +463,13 @@ Vec<cx<T>> vcycle2d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const
     return t;
 }
 
-// Shifted-HSS loop with fused 2D kernels: per HSS step the residual
+// One shifted-HSS step s with fused 2D kernels: the residual
 // rho = c (R - B u) is formed together with the first cycle's
 // pre-smoothing and residual restriction; cycle q's post-smoothing and
 // cycle q+1's pre-smoothing run as one four-sweep pass; the last
-// post-smoothing adds its result into u.
+// post-smoothing adds its result into u (writes it at step 0, u = 0).
 template <typename T>
-void hss_loop2d(helm_t* h, const Layout& Lw, void* ws, int ns) {
+void hss_step2d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const long long N = h->Nl[0];
     Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, N);
     Vec<cx<T>> u = at_ws<cx<T>>(ws, Lw.u, N);
@@ -473,87 +479,53 @@ void hss_loop2d(helm_t* h, const Layout& Lw, void* ws, int ns) {
     const T c = (T)(2.0 * h->k / (h->k + 1.0));
     const Op2<T> L = make_op2<T>(h->coef(HELM_OP_L), h->nl[0], h->omega);
     const Op2<T> Bs = make_op2<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega);
-    zero<T>(h->stream, u.base, N * ns);
+    Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
     if (h->levels == 1) {
         // single level: every cycle is the exact coarse solve
-        for (int s = 0; s < h->hss_steps; ++s) {
-            Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
-            hss_pre0_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, xa, ns);
-            coarse_apply<T>(h->stream, h->d_cinv, h->nc, cst(rho), xb, ns);
-            axpy1<T>(h->stream, N, (T)1, cst(xb), u, ns);
-        }
+        if (s == 0) zero<T>(h->stream, u.base, N * ns);
+        hss_pre0_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, xa, ns);
+        coarse_apply<T>(h->stream, h->d_cinv, h->nc, cst(rho), xb, ns);
+        axpy1<T>(h->stream, N, (T)1, cst(xb), u, ns);
         return;
     }
     const long long N1 = h->Nl[1];
     Vec<cx<T>> b1 = at_ws<cx<T>>(ws, Lw.mg_b[1], N1);
     Vec<cx<T>> x1 = at_ws<cx<T>>(ws, Lw.mg_x[1], N1);
     Vec<cx<T>> t1 = at_ws<cx<T>>(ws, Lw.mg_t[1], N1);
-    if (use_stream(h, 0)) {
-        // register-streaming kernels: cycle q's post-smoothing, cycle q+1's
-        // pre-smoothing and its residual restriction form one pass
-        for (int s = 0; s < h->hss_steps; ++s) {
-            Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
-            stream_pre_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, Vec<const cx<T>>{}, xa, b1, ns);
-            Vec<cx<T>> x = xa, t = xb;
-            for (int q = 0; q < h->cycles; ++q) {
-                Vec<const cx<T>> ec = cst(vcycle2d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
-                const bool last = q == h->cycles - 1;
-                const bool prof = h->prof_on && (h->cycles == 1 || !last);
-                if (prof) h->prof_mark();
-                if (last) {
-                    stream_sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, Vec<cx<T>>{}, true,
-                                        ns);
-                } else {
-                    stream_sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, b1, false, ns);
-                    std::swap(x, t);
-                }
-                if (prof) {
-                    h->prof_mark();
-                    // algorithmic bytes: x, b and e_c (a quarter vector) read,
-                    // x' and b_c (a quarter vector) written; the update pass
-                    // reads u and writes it instead of x' and b_c
-                    h->prof_pending_bytes += sizeof(cx<T>) * (double)N * ns * (last ? 4.25 : 3.5);
-                }
-            }
+    const bool streaming = use_stream(h, 0);
+    if (streaming) stream_pre_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, Vec<const cx<T>>{}, xa, b1, ns);
+    else hss_pre0r_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, xa, b1, ns);
+    Vec<cx<T>> x = xa, t = xb;
+    for (int q = 0; q < h->cycles; ++q) {
+        if (q > 0 && !streaming) resid_restrict2d<T>(h->stream, L, cst(x), cst(rho), b1, ns);
+        Vec<const cx<T>> ec = cst(vcycle2d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
+        const bool last = q == h->cycles - 1;
+        // the profiled kernel is the four-sweep pass (the single two-sweep
+        // update pass when only one cycle is used)
+        const bool prof = h->prof_on && (h->cycles == 1 || !last);
+        if (prof) h->prof_mark();
+        if (last) {
+            if (streaming) stream_sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, Vec<cx<T>>{}, s > 0, ns);
+            else sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, s > 0, ns);
+        } else {
+            if (streaming) stream_sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, b1, false, ns);
+            else sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, false, ns);
+            std::swap(x, t);
         }
-        return;
-    }
-    for (int s = 0; s < h->hss_steps; ++s) {
-        Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
-        hss_pre0r_2d<T>(h->stream, L, Bs, c, uin, cst(R), rho, xa, b1, ns);
-        Vec<cx<T>> x = xa, t = xb;
-        for (int q = 0; q < h->cycles; ++q) {
-            if (q > 0) resid_restrict2d<T>(h->stream, L, cst(x), cst(rho), b1, ns);
-            Vec<const cx<T>> ec = cst(vcycle2d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
-            const bool last = q == h->cycles - 1;
-            // the profiled kernel is the four-sweep pass (the single
-            // two-sweep update pass when only one cycle is used)
-            const bool prof = h->prof_on && (h->cycles == 1 || !last);
-            if (prof) h->prof_mark();
-            if (last) {
-                sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, true, ns);
-            } else {
-                sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, false, ns);
-                std::swap(x, t);
-            }
-            if (prof) {
-                h->prof_mark();
-                // algorithmic bytes: x and b read, e_c read (a quarter of a
-                // vector), x' written; u read and written instead of x' when
-                // it is the update pass
-                h->prof_pending_bytes += sizeof(cx<T>) * (double)N * ns * (last ? 4.25 : 3.25);
-            }
+        if (prof) {
+            h->prof_mark();
+            // algorithmic bytes: x, b and e_c (a quarter vector) read, x'
+            // written, and with the streaming pass b_c (a quarter vector)
+            // written; the update pass reads and writes u instead
+            const double passes = last ? (s > 0 ? 4.25 : 3.25) : (streaming ? 3.5 : 3.25);
+            h->prof_pending_bytes += sizeof(cx<T>) * (double)N * ns * passes;
         }
     }
 }
 
-// Shifted-HSS preconditioner on the slot-major buffers R -> u (precision T).
+// One shifted-HSS step s in 3D: rho = c (R - B u), q V-cycles, u += e.
 template <typename T>
-void hss_loop(helm_t* h, const Layout& Lw, void* ws, int ns) {
-    if (h->dim == 2) {
-        hss_loop2d<T>(h, Lw, ws, ns);
-        return;
-    }
+void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const long long N = h->Nl[0];
     Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, N);
     Vec<cx<T>> u = at_ws<cx<T>>(ws, Lw.u, N);
@@ -561,12 +533,53 @@ void hss_loop(helm_t* h, const Layout& Lw, void* ws, int ns) {
     Vec<cx<T>> e = at_ws<cx<T>>(ws, Lw.mg_x[0], N);
     Vec<cx<T>> t = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
     const T c = (T)(2.0 * h->k / (h->k + 1.0));
-    zero<T>(h->stream, u.base, N * ns);
+    if (s == 0) zero<T>(h->stream, u.base, N * ns);
+    apply_mode<T>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c, cst(u), cst(R), rho, ns);
+    vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns);
+    for (int q = 1; q < h->cycles; ++q) vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
+    axpy1<T>(h->stream, N, (T)1, cst(e), u, ns);
+}
+
+// A range of slots that runs its HSS loop on a stream of its own: the
+// layout's per-slot buffers start at the range's first slot.
+struct SlotGroup {
+    Layout L;
+    int ns;
+    hipStream_t st;
+};
+
+template <typename T>
+Layout shift_slots(const helm_t* h, const Layout& Lw, int s0) {
+    Layout g = Lw;
+    const size_t e = sizeof(cx<T>);
+    for (int l = 0; l < h->levels; ++l) {
+        const size_t d = e * (size_t)s0 * (size_t)h->Nl[l];
+        g.mg_b[l] += d;
+        g.mg_x[l] += d;
+        g.mg_t[l] += d;
+    }
+    g.R += e * (size_t)s0 * (size_t)h->Nl[0];
+    g.u += e * (size_t)s0 * (size_t)h->Nl[0];
+    return g;
+}
+
+// Shifted-HSS preconditioner on the slot-major buffers R -> u (precision T)
+// for every group; the groups' steps are enqueued in turn so that the
+// streams advance together and one group's finest-level passes overlap
+// another's latency-bound coarse levels.
+template <typename T>
+void hss_loop(helm_t* h, void* ws, const SlotGroup* g, int ng) {
+    struct Restore {
+        helm_t* h;
+        hipStream_t st;
+        ~Restore() { h->stream = st; }
+    } restore{h, h->stream};
     for (int s = 0; s < h->hss_steps; ++s) {
-        apply_mode<T>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c, cst(u), cst(R), rho, ns);
-        vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns);
-        for (int q = 1; q < h->cycles; ++q) vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
-        axpy1<T>(h->stream, N, (T)1, cst(e), u, ns);
+        for (int q = 0; q < ng; ++q) {
+            h->stream = g[q].st;
+            if (h->dim == 2) hss_step2d<T>(h, g[q].L, ws, g[q].ns, s);
+            else hss_step3d<T>(h, g[q].L, ws, g[q].ns, s);
+        }
     }
 }
 
@@ -631,38 +644,53 @@ template <typename T>
 void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<cx<T>> z, int ns) {
     const long long N = h->Nl[0];
     copy_cast<T, double>(h->stream, N, v, at_ws<cx<T>>(ws, Lw.R, N), ns);
+    // two slot groups on two streams when there are several columns
+    const int ng = (ns >= 2 && !h->opts.no_split) ? 2 : 1;
+    const int n0 = ng == 2 ? (ns + 1) / 2 : ns;
+    SlotGroup grp[2] = {{Lw, n0, h->stream}, {shift_slots<T>(h, Lw, n0), ns - n0, h->aux_stream}};
+    if (ng == 2) {
+        HIPCHK(hipEventRecord(h->ev_fork, h->stream));
+        HIPCHK(hipStreamWaitEvent(h->aux_stream, h->ev_fork, 0));
+    }
     if (h->prof_on || h->opts.no_graphs) {
-        hss_loop<T>(h, Lw, ws, ns);
+        hss_loop<T>(h, ws, grp, ng);
     } else {
-        // the whole HSS loop (all steps, cycles and levels) replayed as one
-        // captured HIP graph; it reads R and writes u at fixed workspace
-        // addresses, so one graph serves every outer iteration
+        // each group's whole HSS loop (all steps, cycles and levels) is
+        // replayed as one captured HIP graph; it reads R and writes u at fixed
+        // workspace addresses, so one graph serves every outer iteration
         const int tag = (int)sizeof(T);
-        hipGraphExec_t ex = nullptr;
-        for (const auto& g : h->graphs)
-            if (g.ws == ws && g.ns == ns && g.tag == tag && g.cycles == h->cycles) ex = g.exec;
-        if (!ex) {
-            hipStream_t user = h->stream;
-            h->stream = h->cap_stream;
-            hipGraph_t graph = nullptr;
-            HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-            try {
-                hss_loop<T>(h, Lw, ws, ns);
-            } catch (...) {
-                (void)hipStreamEndCapture(h->stream, &graph);
-                if (graph) (void)hipGraphDestroy(graph);
-                h->stream = user;
-                throw;
+        for (int q = 0; q < ng; ++q) {
+            const int s0 = q == 0 ? 0 : n0;
+            hipGraphExec_t ex = nullptr;
+            for (const auto& e : h->graphs)
+                if (e.ws == ws && e.s0 == s0 && e.ns == grp[q].ns && e.tag == tag &&
+                    e.cycles == h->cycles)
+                    ex = e.exec;
+            if (!ex) {
+                hipGraph_t graph = nullptr;
+                SlotGroup cg = grp[q];
+                cg.st = h->cap_stream;
+                HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+                try {
+                    hss_loop<T>(h, ws, &cg, 1);
+                } catch (...) {
+                    (void)hipStreamEndCapture(h->cap_stream, &graph);
+                    if (graph) (void)hipGraphDestroy(graph);
+                    throw;
+                }
+                hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+                HIPCHK(e);
+                e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HIPCHK(e);
+                h->graphs.push_back(helm_s::GraphEntry{ws, s0, grp[q].ns, tag, h->cycles, ex});
             }
-            hipError_t e = hipStreamEndCapture(h->stream, &graph);
-            h->stream = user;
-            HIPCHK(e);
-            e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            HIPCHK(e);
-            h->graphs.push_back(helm_s::GraphEntry{ws, ns, tag, h->cycles, ex});
+            HIPCHK(hipGraphLaunch(ex, grp[q].st));
         }
-        HIPCHK(hipGraphLaunch(ex, h->stream));
+    }
+    if (ng == 2) {
+        HIPCHK(hipEventRecord(h->ev_join, h->aux_stream));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
     }
     copy_cast<T, T>(h->stream, N, cst(at_ws<cx<T>>(ws, Lw.u, N)), z, ns);
 }
@@ -784,6 +812,7 @@ void helm_opts_default(helm_opts* o) {
     o->no_small = 0;
     o->verbose = 0;
     o->no_stream = 0;
+    o->no_split = 0;
 }
 
 const char* helm_strerror(int status) {
@@ -799,6 +828,18 @@ const char* helm_strerror(int status) {
 }
 
 const char* helm_last_error(void) { return g_last_error.c_str(); }
+
+// device objects owned by a handle (null-safe; used on every exit path)
+static void release_handle_objects(helm_t* h) {
+    if (h->d_cinv) (void)hipFree(h->d_cinv);
+    h->d_cinv = nullptr;
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    h->cap_stream = h->aux_stream = nullptr;
+    h->ev_fork = h->ev_join = nullptr;
+}
 
 int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
                 const helm_bc* bc, const helm_opts* opts, void* hip_stream, helm_t** out) {
@@ -906,16 +947,18 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
             return HELM_ENOMEM;
         }
         HIPCHK(hipMemcpy(h->d_cinv, Ah.data(), sizeof(cxd) * Ah.size(), hipMemcpyHostToDevice));
-        // private stream used only to capture the preconditioner graph
+        // private stream used only to capture the preconditioner graph, and
+        // the stream of the second slot group
         HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     } catch (const DevErr&) {
-        if (h->d_cinv) (void)hipFree(h->d_cinv);
-        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        release_handle_objects(h);
         delete h;
         return HELM_EDEVICE;
     } catch (const std::bad_alloc&) {
-        if (h->d_cinv) (void)hipFree(h->d_cinv);
-        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        release_handle_objects(h);
         delete h;
         return HELM_ENOMEM;
     }
@@ -927,10 +970,12 @@ int helm_destroy(helm_t* h) {
     if (!h) return HELM_OK;
     int rc = HELM_OK;
     if (hipStreamSynchronize(h->stream) != hipSuccess) rc = HELM_EDEVICE;
+    if (h->aux_stream && hipStreamSynchronize(h->aux_stream) != hipSuccess) rc = HELM_EDEVICE;
     if (h->d_cinv && hipFree(h->d_cinv) != hipSuccess) rc = HELM_EDEVICE;
+    h->d_cinv = nullptr;
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
-    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    release_handle_objects(h);
     delete h;
     return rc;
 }

@@ -81,15 +81,17 @@ inline Vec<V> contiguous(V* p, long long n) { return Vec<V>{p, n, 0, nullptr}; }
 // corner types of the right-diagonal mesh ((0,0)/(n,n) touch two triangles,
 // (n,0)/(0,n) one), so the Jacobi factors omega / D are precomputed:
 // odC interior, odE edge, odA corners (0,0)/(n,n), odB corners (n,0)/(0,n).
-// On the mesh columns i = 0 and i = n (away from the corners) the element
-// row has centre weight wCe, north and south weights wNe, wAx towards the
-// one horizontal neighbour and wDg towards the one diagonal neighbour.
+// Boundary nodes: with the values outside the mesh taken as zero, the
+// interior stencil at a node on one mesh edge misses the element row by
+// dC on the centre and dN on each of the two neighbours along the edge; at a
+// corner, after both edges' corrections, by kA (corners (0,0) and (n,n)) or
+// kB (corners (n,0) and (0,n)) on the centre.
 template <typename T>
 struct Op2 {
     cx<T> A, Bm, Cg;
     cx<T> wC, wAx, wDg;
     cx<T> odC, odE, odA, odB;
-    cx<T> wCe, wNe;
+    cx<T> dC, dN, kA, kB;
     T omega;
     int n;
 };

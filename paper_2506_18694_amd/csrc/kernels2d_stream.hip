@@ -15,19 +15,22 @@
 // stages); a segment starts its march R rows below its first owned row.
 // The arithmetic per node is the same as in the one-pass kernels.
 //
-// Lanes and rows outside the mesh carry finite garbage (loads there read a
-// clamped, valid address).  No node of the mesh ever depends on it: the
-// boundary rows 0 and n use the per-node element rows, whose weights for
-// the missing neighbours are exact zeros, and the boundary columns 0 and n
-// use their own five-point rows.  Only owned nodes are written.
+// A wavefront whose unit lies away from the mesh boundary applies the
+// interior stencil everywhere; lanes and rows outside the mesh then carry
+// finite garbage (loads read a clamped, valid address) that no mesh node
+// depends on.  A unit that touches a boundary row or column zeroes every
+// value outside the mesh and adds to the interior stencil the boundary
+// corrections of the operator record (dC, dN, kA, kB), which together give
+// the element rows of the edge and corner nodes.  Only owned nodes are
+// written.
 //
-// The march runs in three parts: steps whose stages touch the boundary rows
-// (or lie outside the mesh) are "general" steps; the steps in between run
-// in unrolled blocks of six "fast" steps.  Within a block the three-row
+// The march runs in unrolled blocks of steps: within a block the three-row
 // rings, the queue of right-hand-side rows and three input buffers rotate
 // by renaming registers (the block length is a multiple of every period),
-// and the input row t + 2 is loaded while step t computes.  A general step
-// is the fast step's phase 0 followed by an explicit rotation back.
+// and the input row t + 2 is loaded while step t computes.  A segment's
+// step count is rounded up to whole blocks; the extra steps compute rows
+// past the segment, which are never written.
+#include <algorithm>
 #include <type_traits>
 
 #include "launch.h"
@@ -39,7 +42,6 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int SW = 4;     // independent wavefronts per workgroup
-constexpr int CHUNK = 6;  // fast steps per unrolled block
 
 template <int V>
 using Int = std::integral_constant<int, V>;
@@ -77,6 +79,11 @@ __device__ __forceinline__ cx<T> from_west(cx<T> v) {
     return mk(dpp_shift<DPP_WAVE_SHR1>(v.x), dpp_shift<DPP_WAVE_SHR1>(v.y));
 }
 
+// Marks a rarely taken branch (boundary rows, boundary columns) as having a
+// side effect, so that the compiler keeps it a branch: speculating it would
+// evaluate the boundary formulas for every node of every step.
+__device__ __forceinline__ void keep_branch() { asm volatile(""); }
+
 // A wave-uniform value re-materialised through readfirstlane, so that
 // per-lane selects between such values stay selects of registers (a select
 // between two fields of the operator record would otherwise become a
@@ -102,11 +109,13 @@ template <typename T>
 struct Lanes {
     int i;          // mesh column of this lane (may lie outside 0..n)
     int ic;         // i clamped to 0..n (an address that is always valid)
+    bool inx;       // 0 <= i <= n
     bool colb;      // i == 0 or i == n
     bool lo;        // i == 0
+    T colbf;        // 1 on a boundary column, else 0
     bool any_colb;  // some lane of the wave is a boundary column (uniform)
     cx<T> jf;       // omega / D in the interior rows: boundary column or not
-    cx<T> odE, odA, odB;  // settled factors of the boundary rows
+    cx<T> odC, odE, odA, odB;  // settled factors: interior, boundary rows
 };
 
 template <typename T>
@@ -116,13 +125,16 @@ __device__ __forceinline__ Lanes<T> lanes_of(const Op2<T>& L, int strip, int own
     const int i0 = strip * owned - halo;
     ln.i = i0 + (int)(threadIdx.x % WAVE);
     ln.ic = min(max(ln.i, 0), n);
+    ln.inx = ln.i == ln.ic;
     ln.colb = ln.i == 0 || ln.i == n;
     ln.lo = ln.i == 0;
+    ln.colbf = ln.colb ? (T)1 : (T)0;
     ln.any_colb = (i0 <= 0 && 0 <= i0 + WAVE - 1) || (i0 <= n && n <= i0 + WAVE - 1);
     ln.odE = settle(L.odE);
     ln.odA = settle(L.odA);
     ln.odB = settle(L.odB);
-    ln.jf = sel(ln.colb, ln.odE, settle(L.odC));
+    ln.odC = settle(L.odC);
+    ln.jf = sel(ln.colb, ln.odE, ln.odC);
     return ln;
 }
 
@@ -155,89 +167,61 @@ __device__ __forceinline__ void ring_push(Ring<T>& g, cx<T> nv) {
     g.w[Q::C] = from_west(g.v[Q::C]);
 }
 
-// after a push of phase 0, move the rows back to the layout a phase-0 step
-// expects (newest in slot 2, centre in 1, oldest in 0)
+// a + s t for a real s
 template <typename T>
-__device__ __forceinline__ void ring_rotate(Ring<T>& g) {
-    const cx<T> vn = g.v[0], vc = g.v[2], vo = g.v[1];
-    g.v[2] = vn;
-    g.v[1] = vc;
-    g.v[0] = vo;
-    const cx<T> en = g.e[0], ec = g.e[2];
-    g.e[2] = en;
-    g.e[1] = ec;
-    const cx<T> wc = g.w[2], wo = g.w[1];
-    g.w[1] = wc;
-    g.w[0] = wo;
+__device__ __forceinline__ cx<T> axpy_real(T sc, cx<T> t, cx<T> a) {
+    return mk(fmat(sc, t.x, a.x), fmat(sc, t.y, a.y));
 }
 
-// after writing slot 0 of a queue of depth D at phase 0, move every entry
-// one slot down (the entry k steps old must sit in slot -1 - k mod D)
-template <int D, typename T>
-__device__ __forceinline__ void queue_rotate(cx<T> (&q)[D]) {
-    const cx<T> first = q[0];
-#pragma unroll
-    for (int k = 0; k < D - 1; ++k) q[k] = q[k + 1];
-    q[D - 1] = first;
-}
-
-// (Op v) at the centre row r of g.  GEN: r may be a boundary row.
-template <int P, bool GEN, typename T>
+// (Op v) at the centre row r of g (r uniform across the wave).  EDGE: the
+// wavefront's unit touches a boundary row or column and holds zeros outside
+// the mesh; otherwise every node it computes is an interior node.
+template <int P, bool EDGE, typename T>
 __device__ __forceinline__ cx<T> ring_apply(const Op2<T>& op, const Ring<T>& g, const Lanes<T>& ln,
                                             int r) {
     using Q = Slots<P>;
     const cx<T> c = g.v[Q::C], nn = g.v[Q::N], ss = g.v[Q::O];
     const cx<T> ee = g.e[Q::C], ww = g.w[Q::C], ne = g.e[Q::N], sw = g.w[Q::O];
-    if (GEN && (r == 0 || r == op.n)) {
-        // boundary row: the element row of every node (zero weights towards
-        // the missing neighbours)
-        const Row7<T> w = row_weights(op, ln.i, r);
-        cx<T> acc = w.w[0] * c;
-        acc = cfma(w.w[1], ee, acc);
-        acc = cfma(w.w[2], ww, acc);
-        acc = cfma(w.w[3], nn, acc);
-        acc = cfma(w.w[4], ss, acc);
-        acc = cfma(w.w[5], ne, acc);
-        acc = cfma(w.w[6], sw, acc);
-        return acc;
-    }
     cx<T> acc = cfma(op.wDg, ne + sw, cfma(op.wAx, (ee + ww) + (nn + ss), op.wC * c));
-    if (ln.any_colb) {
-        if (ln.colb) {
-            // boundary column: one horizontal and one diagonal neighbour
-            const cx<T> h = sel(ln.lo, ee, ww), d = sel(ln.lo, ne, sw);
-            acc = cfma(op.wDg, d, cfma(op.wAx, h, cfma(op.wNe, nn + ss, op.wCe * c)));
+    if (EDGE) {
+        // boundary column: the two neighbours along it and the centre
+        acc = axpy_real(ln.colbf, cfma(op.dN, nn + ss, op.dC * c), acc);
+        if (r == 0 || r == op.n) {
+            keep_branch();
+            // boundary row, and at its two corners the remaining centre term
+            acc = acc + cfma(op.dN, ee + ww, op.dC * c);
+            acc = axpy_real(ln.colbf, sel(ln.lo == (r == 0), op.kA, op.kB) * c, acc);
         }
     }
     return acc;
 }
 
 // omega / D at row r
-template <bool GEN, typename T>
+template <bool EDGE, typename T>
 __device__ __forceinline__ cx<T> ring_jf(const Lanes<T>& ln, int r, int n) {
-    if (GEN && (r == 0 || r == n))
+    if (!EDGE) return ln.odC;
+    if (r == 0 || r == n) {
+        keep_branch();
         return sel(ln.colb, sel(ln.lo == (r == 0), ln.odA, ln.odB), ln.odE);
+    }
     return ln.jf;
 }
 
 // P^T r at the fine node (2I, 2J) = centre row rr of g:
-// r(2I, 2J) + (1/2) (sum over its fine edge neighbours inside the mesh)
-template <int P, bool GEN, typename T>
-__device__ __forceinline__ cx<T> ring_restrict(const Ring<T>& g, const Lanes<T>& ln, int rr, int n) {
+// r(2I, 2J) + (1/2) (sum over its six fine edge neighbours; those outside
+// the mesh hold zero in a boundary unit)
+template <int P, typename T>
+__device__ __forceinline__ cx<T> ring_restrict(const Ring<T>& g) {
     using Q = Slots<P>;
-    const cx<T> c = g.v[Q::C], nn = g.v[Q::N], ss = g.v[Q::O];
-    const cx<T> ee = g.e[Q::C], ww = g.w[Q::C], ne = g.e[Q::N], sw = g.w[Q::O];
-    const bool rowb = GEN && (rr == 0 || rr == n);
-    cx<T> s6;
-    if (rowb || ln.any_colb) {
-        const cx<T> z = zero_cx<T>();
-        const bool mE = ln.i < n, mW = ln.i > 0, mN = rr < n, mS = rr > 0;
-        s6 = ((sel(mE, ee, z) + sel(mW, ww, z)) + (sel(mN, nn, z) + sel(mS, ss, z))) +
-             (sel(mE && mN, ne, z) + sel(mW && mS, sw, z));
-    } else {
-        s6 = ((ee + ww) + (nn + ss)) + (ne + sw);
-    }
-    return cfma(mk((T)0.5, (T)0), s6, c);
+    const cx<T> s6 = ((g.e[Q::C] + g.w[Q::C]) + (g.v[Q::N] + g.v[Q::O])) + (g.e[Q::N] + g.w[Q::O]);
+    return cfma(mk((T)0.5, (T)0), s6, g.v[Q::C]);
+}
+
+// in a boundary unit: zero outside the mesh (row r uniform)
+template <bool EDGE, typename T>
+__device__ __forceinline__ cx<T> clip(cx<T> v, const Lanes<T>& ln, int r, int n) {
+    if (!EDGE) return v;
+    return sel(ln.inx && r >= 0 && r <= n, v, zero_cx<T>());
 }
 
 struct Unit {
@@ -246,7 +230,10 @@ struct Unit {
 
 __device__ __forceinline__ bool unit_of(const StreamGrid& gr, Unit& u) {
     const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
-    const unsigned id = blk * SW + (threadIdx.x / WAVE);
+    // the wavefront's index within the workgroup, made visibly uniform so
+    // that the unit, the rows and every branch on them stay scalar
+    const unsigned wid = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const unsigned id = blk * SW + wid;
     if (id >= gr.units) return false;
     const unsigned per_slot = gr.strips * gr.segs;
     u.slot = (int)(id / per_slot);
@@ -289,7 +276,7 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     constexpr int OWN = WAVE - 2 * HALO;
     constexpr int NR = S + (RESID ? 2 : 0);
     constexpr int NB = (S + (RESID ? 2 : 1) <= 3) ? 3 : 6;  // queue of b rows
-    static_assert(CHUNK % NB == 0 && CHUNK % 3 == 0, "block length must cover every period");
+    constexpr int CHUNK = NB;  // steps per block: a multiple of 3 and of NB
     Unit un;
     if (!unit_of(gr, un)) return;
     const int n = L.n;
@@ -332,21 +319,22 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     };
 
     // one step of phase P: input row t, every stage one row on
-    auto step = [&](auto pc, auto gc, const SweepIn<T, PROLONG, UPDATE>& in, int t) {
+    auto step = [&](auto pc, auto ec, const SweepIn<T, PROLONG, UPDATE>& in, int t) {
         constexpr int P = decltype(pc)::value;
-        constexpr bool GEN = decltype(gc)::value;
+        constexpr bool EDGE = decltype(ec)::value;
         using Q = Slots<P>;
         cx<T> x0 = in.x;
         if (PROLONG) x0 = cfma(mk((T)0.5, (T)0), in.e0 + in.e1, x0);
-        ring_push<P>(rg[0], x0);
+        ring_push<P>(rg[0], clip<EDGE>(x0, ln, t, n));
         bq[P % NB] = in.b;
 #pragma unroll
         for (int s = 1; s <= S; ++s) {
             const int r = t - s;
             const Ring<T>& g = rg[s - 1];
             const cx<T> br = bq[qslot<NB>(P, s)];
-            const cx<T> v =
-                cfma(ring_jf<GEN>(ln, r, n), br - ring_apply<P, GEN>(L, g, ln, r), g.v[Q::C]);
+            const cx<T> v = clip<EDGE>(
+                cfma(ring_jf<EDGE>(ln, r, n), br - ring_apply<P, EDGE>(L, g, ln, r), g.v[Q::C]), ln,
+                r, n);
             if (s < S) {
                 ring_push<P>(rg[s], v);
             } else {
@@ -361,53 +349,42 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         if (RESID) {
             // residual of the final iterate, row t - S - 1
             const int r = t - S - 1;
-            const cx<T> rv = bq[qslot<NB>(P, S + 1)] - ring_apply<P, GEN>(L, rg[S], ln, r);
-            ring_push<P>(rg[S + 1], rv);
+            const cx<T> rv = bq[qslot<NB>(P, S + 1)] - ring_apply<P, EDGE>(L, rg[S], ln, r);
+            ring_push<P>(rg[S + 1], clip<EDGE>(rv, ln, r, n));
             // restriction at the fine row t - S - 2 when it is even
             const int rr = t - S - 2;
             if (!(rr & 1) && rr >= y0 && rr < y1) {
-                const cx<T> v = ring_restrict<P, GEN>(rg[S + 1], ln, rr, n);
+                const cx<T> v = ring_restrict<P>(rg[S + 1]);
                 if (own && !(ln.i & 1)) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
             }
         }
-        if (GEN) {
-#pragma unroll
-            for (int k = 0; k < NR; ++k) ring_rotate(rg[k]);
-            queue_rotate<NB>(bq);
-        }
     };
 
-    // steps whose stages all lie in mesh rows 1..n-1 run as fast steps
-    const int tf0 = max(tb, DEPTH + 1), tf1 = min(te, n);
-    int t = tb;
-    for (; t < tf0 && t <= te; ++t) {
-        SweepIn<T, PROLONG, UPDATE> in;
-        load(in, t);
-        step(Int<0>{}, Bool<true>{}, in, t);
-    }
-    if (tf1 - t + 1 >= CHUNK) {
-        SweepIn<T, PROLONG, UPDATE> buf[3];
-        load(buf[0], t);
-        load(buf[1], t + 1);
-        auto fast = [&](auto pc) {
+    SweepIn<T, PROLONG, UPDATE> buf[3];
+    load(buf[0], tb);
+    load(buf[1], tb + 1);
+    auto march = [&](auto ec) {
+        auto block = [&](auto pc, int t) {
             constexpr int P = decltype(pc)::value;
             load(buf[(P + 2) % 3], t + P + 2);
-            step(pc, Bool<false>{}, buf[P % 3], t + P);
+            step(pc, ec, buf[P % 3], t + P);
         };
-        for (; t + CHUNK - 1 <= tf1; t += CHUNK) {
-            fast(Int<0>{});
-            fast(Int<1>{});
-            fast(Int<2>{});
-            fast(Int<3>{});
-            fast(Int<4>{});
-            fast(Int<5>{});
+        for (int t = tb; t <= te; t += CHUNK) {
+            block(Int<0>{}, t);
+            block(Int<1>{}, t);
+            block(Int<2>{}, t);
+            if constexpr (CHUNK == 6) {
+                block(Int<3>{}, t);
+                block(Int<4>{}, t);
+                block(Int<5>{}, t);
+            }
         }
-    }
-    for (; t <= te; ++t) {
-        SweepIn<T, PROLONG, UPDATE> in;
-        load(in, t);
-        step(Int<0>{}, Bool<true>{}, in, t);
-    }
+    };
+    // a unit whose stencil rows (tb - DEPTH .. its last step) or columns
+    // include a mesh boundary runs the boundary-aware code
+    const int rlo = tb - DEPTH, rhi = tb + ((te - tb) / CHUNK + 1) * CHUNK - 1;
+    if (ln.any_colb || (rlo <= 0 && 0 <= rhi) || (rlo <= n && n <= rhi)) march(Bool<true>{});
+    else march(Bool<false>{});
 }
 
 // ---- k_stream_pre -----------------------------------------------------------
@@ -463,16 +440,16 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         if (HSS == 1) in.u = load_raw(u, ln.ic, t, n);
     };
 
-    auto step = [&](auto pc, auto gc, const PreIn<T>& in, int t) {
+    auto step = [&](auto pc, auto ec, const PreIn<T>& in, int t) {
         constexpr int P = decltype(pc)::value;
-        constexpr bool GEN = decltype(gc)::value;
+        constexpr bool EDGE = decltype(ec)::value;
         using Q = Slots<P>;
         cx<T> bnew;
         int rb;  // row of bnew
         if (HSS == 1) {
-            ring_push<P>(gu, in.u);
+            ring_push<P>(gu, clip<EDGE>(in.u, ln, t, n));
             rb = t - 1;
-            bnew = c * (rq[(P + 1) % 2] - ring_apply<P, GEN>(Bs, gu, ln, rb));
+            bnew = c * (rq[(P + 1) % 2] - ring_apply<P, EDGE>(Bs, gu, ln, rb));
             rq[P % 2] = in.s;
         } else if (HSS == 2) {
             rb = t;
@@ -484,69 +461,57 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         if (HSS != 0 && own && rb >= y0 && rb < y1) rho[(long long)rb * np + ln.i] = bnew;
         bq[P % 3] = bnew;
         // first sweep (pointwise): row rb
-        ring_push<P>(g1, ring_jf<GEN>(ln, rb, n) * bnew);
+        ring_push<P>(g1, clip<EDGE>(ring_jf<EDGE>(ln, rb, n) * bnew, ln, rb, n));
         // second sweep: row rb - 1, written
         {
             const int r = rb - 1;
-            const cx<T> v = cfma(ring_jf<GEN>(ln, r, n),
-                                 bq[qslot<3>(P, 1)] - ring_apply<P, GEN>(L, g1, ln, r), g1.v[Q::C]);
+            const cx<T> v =
+                cfma(ring_jf<EDGE>(ln, r, n), bq[qslot<3>(P, 1)] - ring_apply<P, EDGE>(L, g1, ln, r),
+                     g1.v[Q::C]);
             if (own && r >= y0 && r < y1) x[(long long)r * np + ln.i] = v;
-            ring_push<P>(g2, v);
+            ring_push<P>(g2, clip<EDGE>(v, ln, r, n));
         }
         // residual: row rb - 2
         {
             const int r = rb - 2;
-            ring_push<P>(gr3, bq[qslot<3>(P, 2)] - ring_apply<P, GEN>(L, g2, ln, r));
+            ring_push<P>(gr3, clip<EDGE>(bq[qslot<3>(P, 2)] - ring_apply<P, EDGE>(L, g2, ln, r), ln, r, n));
         }
         // restriction at the fine row rb - 3 when even
         {
             const int rr = rb - 3;
             if (!(rr & 1) && rr >= y0 && rr < y1) {
-                const cx<T> v = ring_restrict<P, GEN>(gr3, ln, rr, n);
+                const cx<T> v = ring_restrict<P>(gr3);
                 if (own && !(ln.i & 1)) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
             }
         }
-        if (GEN) {
-            if (HSS == 1) ring_rotate(gu);
-            ring_rotate(g1);
-            ring_rotate(g2);
-            ring_rotate(gr3);
-            queue_rotate<3>(bq);
-            queue_rotate<2>(rq);
-        }
     };
 
-    // fast steps: every stage row in 1..n-1
-    const int tf0 = max(tb, DEPTH + 1), tf1 = min(te, n - 1 + DB);
-    int t = tb;
-    for (; t < tf0 && t <= te; ++t) {
-        PreIn<T> in;
-        load(in, t);
-        step(Int<0>{}, Bool<true>{}, in, t);
-    }
-    if (tf1 - t + 1 >= CHUNK) {
-        PreIn<T> buf[3];
-        load(buf[0], t);
-        load(buf[1], t + 1);
-        auto fast = [&](auto pc) {
+    constexpr int CHUNK = HSS == 1 ? 6 : 3;  // a multiple of 3 and of the R queue's 2
+    PreIn<T> buf[3];
+    load(buf[0], tb);
+    load(buf[1], tb + 1);
+    auto march = [&](auto ec) {
+        auto block = [&](auto pc, int t) {
             constexpr int P = decltype(pc)::value;
             load(buf[(P + 2) % 3], t + P + 2);
-            step(pc, Bool<false>{}, buf[P % 3], t + P);
+            step(pc, ec, buf[P % 3], t + P);
         };
-        for (; t + CHUNK - 1 <= tf1; t += CHUNK) {
-            fast(Int<0>{});
-            fast(Int<1>{});
-            fast(Int<2>{});
-            fast(Int<3>{});
-            fast(Int<4>{});
-            fast(Int<5>{});
+        for (int t = tb; t <= te; t += CHUNK) {
+            block(Int<0>{}, t);
+            block(Int<1>{}, t);
+            block(Int<2>{}, t);
+            if constexpr (CHUNK == 6) {
+                block(Int<3>{}, t);
+                block(Int<4>{}, t);
+                block(Int<5>{}, t);
+            }
         }
-    }
-    for (; t <= te; ++t) {
-        PreIn<T> in;
-        load(in, t);
-        step(Int<0>{}, Bool<true>{}, in, t);
-    }
+    };
+    // a unit whose stencil rows (tb - DEPTH .. its last step) or columns
+    // include a mesh boundary runs the boundary-aware code
+    const int rlo = tb - DEPTH, rhi = tb + ((te - tb) / CHUNK + 1) * CHUNK - 1;
+    if (ln.any_colb || (rlo <= 0 && 0 <= rhi) || (rlo <= n && n <= rhi)) march(Bool<true>{});
+    else march(Bool<false>{});
 }
 
 }  // namespace
@@ -561,16 +526,24 @@ StreamGrid stream_grid(int n, int halo, int ns, int H) {
     return g;
 }
 
-// Segment height: the tallest of 64, 32, 16, 8 rows that still gives every
-// compute unit several wavefronts.
+// Segment height.  A segment of H rows costs about H + 2 halo + 1 steps of
+// one wavefront; the kernel takes at least as long as one wavefront's chain
+// of steps (about 1.2 us per step) and as long as all wavefronts' steps at
+// the chip's throughput (about 1400 wavefront-steps per microsecond).  The
+// height minimising the larger of the two is used.
 static int stream_rows(int n, int halo, int ns) {
-    int H = 64;
-    while (H > 8) {
+    int best = 64;
+    double tbest = 1e30;
+    for (int H = 4; H <= 128; H *= 2) {
         const StreamGrid g = stream_grid(n, halo, ns, H);
-        if (g.units >= 2048) break;
-        H /= 2;
+        const double steps = H + 2.0 * halo + 1.0;
+        const double t = std::max(g.units * steps / 1400.0, steps * 1.2);
+        if (t < tbest) {
+            tbest = t;
+            best = H;
+        }
     }
-    return H;
+    return best;
 }
 
 static unsigned stream_blocks(const StreamGrid& g) { return (g.units + SW - 1) / SW; }

@@ -176,3 +176,19 @@ def test_load_nodal_is_mass_times_source():
     b = to_host(s.load_nodal(torch.from_numpy(f).cuda()))
     K, M, MG = fem.assemble_2d(64)
     assert rel_err(b, np.stack([M @ fi for fi in f])) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("graphs", [True, False])
+def test_split_column_groups_match_one_batch(prec, graphs):
+    """Several columns run as two slot groups on two streams (the default)
+    or as one batch: each column's arithmetic is the same, so the results
+    agree bit for bit; an odd column count splits unevenly."""
+    n, levels, k = 128, 5, 12.0
+    v = W.random_complex((3, (n + 1) ** 2), 23)
+    outs = []
+    for split in (True, False):
+        s = _solver(2, n, levels, k, k, prec, restart=4, mg_cycles=2, graphs=graphs, split=split)
+        outs.append(to_host(s.precondition(to_dev(v))))
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
