@@ -63,7 +63,7 @@ def stored_traffic(workload, precision):
     return rec.get("bytes_per_launch")
 
 
-def run_solves(W, name, precision, steps, warmup, tol, max_outer=0, streaming=True, split=True):
+def run_solves(W, name, precision, steps, warmup, tol, max_outer=0, streaming=True, split=False):
     import torch
     from paper_2506_18694_amd import Solver
     w = W.WORKLOADS[name]
@@ -192,9 +192,9 @@ def main():
     ap.add_argument("--workload", default="p1-1024-k100")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-split", action="store_true",
-                    help="run the preconditioner of all right-hand sides as one batch on one "
-                         "stream (for comparison)")
+    ap.add_argument("--split", action="store_true",
+                    help="run the preconditioner's right-hand sides as two groups on two "
+                         "streams (for comparison; the default is one batch on one stream)")
     ap.add_argument("--lds-kernels", action="store_true",
                     help="run the large 2D levels with the LDS-tiled kernels instead of the "
                          "register-streaming ones (for comparison)")
@@ -240,7 +240,7 @@ def main():
         args.no_fp32 = args.no_cpu_baseline = True
     r = run_solves(W, name, main_prec, args.steps, args.warmup, args.tol,
                    max_outer=3 if args.profile_run else 0, streaming=not args.lds_kernels,
-                   split=not args.no_split)
+                   split=args.split)
     ms = r["elapsed"] / args.steps * 1e3
     value = r["N"] * r["nrhs"] / (ms / 1e3)
     sw_ms = sum(st["sweep_ms"] for st in r["stats"])
@@ -272,7 +272,7 @@ def main():
            "roofline": roof}
     if not args.no_fp32 and main_prec == "fp64":
         r32 = run_solves(W, name, "fp32", 1, 1, args.tol, streaming=not args.lds_kernels,
-                         split=not args.no_split)
+                         split=args.split)
         ms32 = r32["elapsed"] * 1e3
         v32 = r32["N"] * r32["nrhs"] / (ms32 / 1e3)
         s32 = r32["stats"][0]

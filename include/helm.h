@@ -102,8 +102,11 @@ typedef struct {
     int    restart;    /* FGMRES basis size; 0 = 3*ceil(k) + 30, max 2000    */
     int    max_outer;  /* outer iteration cap; 0 = 4 * restart               */
     int    x0_given;   /* 1: x holds the initial guess on entry, else x0 = 0 */
-    int    profile;    /* 1: time every finest-level Jacobi sweep of the
-                          solve with HIP events (fills the sweep_* stats)    */
+    int    profile;    /* 1: time the finest-level smoothing launches of the
+                          solve with HIP events (2D: the four-sweep passes;
+                          3D: each Jacobi sweep; fills the sweep_* stats).
+                          A timed solve runs its preconditioner eagerly,
+                          without the captured graphs                       */
     int    mg_cycles;  /* V-cycles per inner HSS solve (each after the first
                           starts from the previous iterate).  0 = automatic:
                           with exact inner solves the HSS error contracts by
@@ -128,11 +131,11 @@ typedef struct {
                           streaming kernels (one wavefront marches up a
                           strip of 64 columns, every sweep a pipeline stage
                           one row behind the previous one)                   */
-    int    no_split;   /* 1: run the preconditioner of all columns as one
-                          batch; by default, with two or more columns, the
-                          columns are split into two groups whose HSS loops
-                          run on two streams, so that one group's finest-
-                          level passes overlap the other's coarse levels    */
+    int    split;      /* 1: with two or more columns, split them into two
+                          groups whose HSS loops run on two streams (one
+                          group's finest-level passes can overlap the
+                          other's latency-bound coarse levels); by default
+                          all columns run as one batch on one stream        */
 } helm_opts;
 
 typedef struct {
@@ -147,11 +150,13 @@ typedef struct {
     double solve_ms;             /* wall time of helm_solve                  */
     double precond_ms;           /* device time inside the preconditioner    */
     double sweep_ms;             /* profile=1: summed device time of the
-                                    finest-level Jacobi sweep launches        */
+                                    timed smoothing launches (see profile)    */
     long long sweep_launches;    /* profile=1: number of those launches       */
-    double sweep_bytes;          /* profile=1: algorithmic bytes they move:
-                                    read x, read b, write x' = 3 vectors per
-                                    right-hand side per launch                */
+    double sweep_bytes;          /* profile=1: algorithmic bytes they move per
+                                    right-hand side: x and b read, x' written;
+                                    2D adds the coarse correction read and the
+                                    coarse residual written (a quarter vector
+                                    each)                                      */
     int    mg_cycles;            /* V-cycles per inner HSS solve used          */
     double vcycle_rate;          /* measured V-cycle contraction (automatic
                                     mode; 0 when mg_cycles was given)         */

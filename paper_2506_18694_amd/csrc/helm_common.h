@@ -23,18 +23,18 @@ using cxf = cx<float>;
 
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> mk(T re, T im) { cx<T> r; r.x = re; r.y = im; return r; }
+__host__ __device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
-    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return mk(fmat(a.x, b.x, -(a.y * b.y)), fmat(a.x, b.y, a.y * b.x));
 }
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return mk(s * a.x, s * a.y); }
-__host__ __device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
-__host__ __device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }
 // a * b + c
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {

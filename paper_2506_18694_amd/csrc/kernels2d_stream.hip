@@ -10,18 +10,20 @@
 // diagonal "/" neighbours) come from the adjacent lanes through wave-wide
 // DPP lane shifts.  Nothing is staged in LDS and there are no barriers.
 //
-// Each stage loses one lane of validity on each side, so a strip computes 64
-// columns and owns the 64 - 2R in the middle (R = number of neighbour
-// stages); a segment starts its march R rows below its first owned row.
-// The arithmetic per node is the same as in the one-pass kernels.
+// Each stage loses one lane of validity on each side that borders another
+// strip, so a middle strip computes 64 columns and owns the 64 - 2R in the
+// middle (R = number of neighbour stages).  The first strip starts at column
+// 0 and the last ends at column n in lane 63: there the lane shift fills the
+// missing neighbour with zero, nothing is lost, and the strip owns up to the
+// boundary.  A segment starts its march R rows below its first owned row.
 //
-// A wavefront whose unit lies away from the mesh boundary applies the
-// interior stencil everywhere; lanes and rows outside the mesh then carry
-// finite garbage (loads read a clamped, valid address) that no mesh node
-// depends on.  A unit that touches a boundary row or column zeroes every
-// value outside the mesh and adds to the interior stencil the boundary
-// corrections of the operator record (dC, dN, kA, kB), which together give
-// the element rows of the edge and corner nodes.  Only owned nodes are
+// Values outside the mesh are zero where a stencil can see them: beyond the
+// first and last column through the lane shift, below row 0 and above row n
+// by clearing the stage outputs of those rows (only in the first and last
+// blocks of steps of a segment that reaches them), and, when a single strip
+// is wider than the mesh, in its lanes past column n.  The interior stencil
+// plus the boundary corrections of the operator record (dC, dN, kA, kB) then
+// gives the element rows of the edge and corner nodes.  Only owned nodes are
 // written.
 //
 // The march runs in unrolled blocks of steps: within a block the three-row
@@ -30,7 +32,18 @@
 // and the input row t + 2 is loaded while step t computes.  A segment's
 // step count is rounded up to whole blocks; the extra steps compute rows
 // past the segment, which are never written.
+//
+// The rows next to a segment's ends run through code with the boundary
+// handling compiled in, the others through code without it, and where
+// those ends fall depends on the segment height, which is chosen by
+// timing.  So that every node gets the same roundings whatever the
+// height, nothing in this file lets the compiler fuse a product into a
+// following sum on its own: every fused multiply-add is written out.
+#pragma clang fp contract(off)
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "launch.h"
@@ -114,22 +127,51 @@ struct Lanes {
     bool lo;        // i == 0
     T colbf;        // 1 on a boundary column, else 0
     bool any_colb;  // some lane of the wave is a boundary column (uniform)
+    int lo_own, hi_own;  // owned columns [lo_own, hi_own)
     cx<T> jf;       // omega / D in the interior rows: boundary column or not
     cx<T> odC, odE, odA, odB;  // settled factors: interior, boundary rows
 };
 
+// Strip geometry (see the top of the file): owned widths of the first and of
+// the middle strips, both even so that every coarse column has one owner.
+__host__ __device__ inline int strip_first(int halo) { return (WAVE - halo) & ~1; }
+__host__ __device__ inline int strip_mid(int halo) { return (WAVE - 2 * halo) & ~1; }
+__host__ __device__ inline int strip_count(int n, int halo) {
+    if (n + 1 <= WAVE) return 1;
+    // columns left after the first strip and a last strip of full width
+    const int rest = n + 1 - strip_first(halo) - (WAVE - halo);
+    return 2 + (rest > 0 ? (rest + strip_mid(halo) - 1) / strip_mid(halo) : 0);
+}
+
 template <typename T>
-__device__ __forceinline__ Lanes<T> lanes_of(const Op2<T>& L, int strip, int owned, int halo) {
+__device__ __forceinline__ Lanes<T> lanes_of(const Op2<T>& L, int strip, int strips, int halo) {
     const int n = L.n;
     Lanes<T> ln;
-    const int i0 = strip * owned - halo;
+    int i0;
+    if (strips == 1) {
+        i0 = 0;
+        ln.lo_own = 0;
+        ln.hi_own = n + 1;
+    } else if (strip == 0) {
+        i0 = 0;
+        ln.lo_own = 0;
+        ln.hi_own = strip_first(halo);
+    } else if (strip == strips - 1) {
+        i0 = n - (WAVE - 1);
+        ln.lo_own = strip_first(halo) + (strips - 2) * strip_mid(halo);
+        ln.hi_own = n + 1;
+    } else {
+        ln.lo_own = strip_first(halo) + (strip - 1) * strip_mid(halo);
+        ln.hi_own = ln.lo_own + strip_mid(halo);
+        i0 = ln.lo_own - halo;
+    }
     ln.i = i0 + (int)(threadIdx.x % WAVE);
     ln.ic = min(max(ln.i, 0), n);
     ln.inx = ln.i == ln.ic;
     ln.colb = ln.i == 0 || ln.i == n;
     ln.lo = ln.i == 0;
     ln.colbf = ln.colb ? (T)1 : (T)0;
-    ln.any_colb = (i0 <= 0 && 0 <= i0 + WAVE - 1) || (i0 <= n && n <= i0 + WAVE - 1);
+    ln.any_colb = strips == 1 || strip == 0 || strip == strips - 1;
     ln.odE = settle(L.odE);
     ln.odA = settle(L.odA);
     ln.odB = settle(L.odB);
@@ -173,38 +215,46 @@ __device__ __forceinline__ cx<T> axpy_real(T sc, cx<T> t, cx<T> a) {
     return mk(fmat(sc, t.x, a.x), fmat(sc, t.y, a.y));
 }
 
-// (Op v) at the centre row r of g (r uniform across the wave).  EDGE: the
-// wavefront's unit touches a boundary row or column and holds zeros outside
-// the mesh; otherwise every node it computes is an interior node.
-template <int P, bool EDGE, typename T>
+// What a wavefront's unit touches: boundary columns (0 or n among its
+// lanes) and/or boundary rows (0 or n among its stencil rows).  A unit that
+// touches a boundary holds zeros outside the mesh and adds the boundary
+// corrections; an interior unit applies the interior stencil everywhere.
+constexpr int TOUCH_COL = 1, TOUCH_ROW = 2, CLIP_LANES = 4;
+
+// (Op v) at the centre row r of g (r uniform across the wave)
+template <int P, int MODE, typename T>
 __device__ __forceinline__ cx<T> ring_apply(const Op2<T>& op, const Ring<T>& g, const Lanes<T>& ln,
                                             int r) {
     using Q = Slots<P>;
     const cx<T> c = g.v[Q::C], nn = g.v[Q::N], ss = g.v[Q::O];
     const cx<T> ee = g.e[Q::C], ww = g.w[Q::C], ne = g.e[Q::N], sw = g.w[Q::O];
     cx<T> acc = cfma(op.wDg, ne + sw, cfma(op.wAx, (ee + ww) + (nn + ss), op.wC * c));
-    if (EDGE) {
+    if (MODE & TOUCH_COL) {
         // boundary column: the two neighbours along it and the centre
         acc = axpy_real(ln.colbf, cfma(op.dN, nn + ss, op.dC * c), acc);
+    }
+    if (MODE & TOUCH_ROW) {
         if (r == 0 || r == op.n) {
             keep_branch();
             // boundary row, and at its two corners the remaining centre term
             acc = acc + cfma(op.dN, ee + ww, op.dC * c);
-            acc = axpy_real(ln.colbf, sel(ln.lo == (r == 0), op.kA, op.kB) * c, acc);
+            if (MODE & TOUCH_COL)
+                acc = axpy_real(ln.colbf, sel(ln.lo == (r == 0), op.kA, op.kB) * c, acc);
         }
     }
     return acc;
 }
 
 // omega / D at row r
-template <bool EDGE, typename T>
+template <int MODE, typename T>
 __device__ __forceinline__ cx<T> ring_jf(const Lanes<T>& ln, int r, int n) {
-    if (!EDGE) return ln.odC;
-    if (r == 0 || r == n) {
-        keep_branch();
-        return sel(ln.colb, sel(ln.lo == (r == 0), ln.odA, ln.odB), ln.odE);
+    if (MODE & TOUCH_ROW) {
+        if (r == 0 || r == n) {
+            keep_branch();
+            return sel(ln.colb, sel(ln.lo == (r == 0), ln.odA, ln.odB), ln.odE);
+        }
     }
-    return ln.jf;
+    return (MODE & TOUCH_COL) ? ln.jf : ln.odC;
 }
 
 // P^T r at the fine node (2I, 2J) = centre row rr of g:
@@ -218,28 +268,60 @@ __device__ __forceinline__ cx<T> ring_restrict(const Ring<T>& g) {
 }
 
 // in a boundary unit: zero outside the mesh (row r uniform)
-template <bool EDGE, typename T>
+template <int MODE, typename T>
 __device__ __forceinline__ cx<T> clip(cx<T> v, const Lanes<T>& ln, int r, int n) {
-    if (!EDGE) return v;
-    return sel(ln.inx && r >= 0 && r <= n, v, zero_cx<T>());
+    if (MODE & CLIP_LANES) v = sel(ln.inx, v, zero_cx<T>());
+    if (MODE & TOUCH_ROW) {
+        if (r < 0 || r > n) {
+            keep_branch();
+            v = zero_cx<T>();
+        }
+    }
+    return v;
 }
 
 struct Unit {
     int slot, strip, seg;
 };
 
+// Units that touch the mesh boundary (first and last strip, first and last
+// segment) run the slower boundary code; they are dispatched first, spread
+// over all XCDs, so that they do not finish last.  The interior units follow,
+// each XCD taking a contiguous range of them (neighbouring strips and
+// segments share halo rows in one L2).
 __device__ __forceinline__ bool unit_of(const StreamGrid& gr, Unit& u) {
-    const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
     // the wavefront's index within the workgroup, made visibly uniform so
     // that the unit, the rows and every branch on them stay scalar
     const unsigned wid = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const unsigned S = gr.strips, G = gr.segs;
+    const bool split = S > 2 && G > 2;
+    const unsigned I = split ? (S - 2) * (G - 2) : 0;  // interior units per slot
+    const unsigned E = S * G - I;                      // boundary units per slot
+    if (blockIdx.x < gr.eblocks) {
+        const unsigned id = blockIdx.x * SW + wid;
+        if (id >= gr.edge_units) return false;
+        u.slot = (int)(id / E);
+        const unsigned e = id % E;
+        if (!split) {
+            u.seg = (int)(e / S);
+            u.strip = (int)(e % S);
+        } else if (e < 2 * S) {
+            u.seg = e < S ? 0 : (int)G - 1;
+            u.strip = (int)(e % S);
+        } else {
+            const unsigned k = e - 2 * S;
+            u.seg = 1 + (int)(k / 2);
+            u.strip = (k & 1) ? (int)S - 1 : 0;
+        }
+        return true;
+    }
+    const unsigned blk = xcd_remap(blockIdx.x - gr.eblocks, gridDim.x - gr.eblocks);
     const unsigned id = blk * SW + wid;
-    if (id >= gr.units) return false;
-    const unsigned per_slot = gr.strips * gr.segs;
-    u.slot = (int)(id / per_slot);
-    const unsigned r = id % per_slot;
-    u.seg = (int)(r / gr.strips);
-    u.strip = (int)(r % gr.strips);
+    if (id >= gr.units - gr.edge_units) return false;
+    u.slot = (int)(id / I);
+    const unsigned r = id % I;
+    u.seg = 1 + (int)(r / (S - 2));
+    u.strip = 1 + (int)(r % (S - 2));
     return true;
 }
 
@@ -273,16 +355,14 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     Vec<cx<T>> Bc, StreamGrid gr) {
     constexpr int DEPTH = S + (RESID ? 2 : 0);  // lag of the deepest stage
     constexpr int HALO = DEPTH;
-    constexpr int OWN = WAVE - 2 * HALO;
     constexpr int NR = S + (RESID ? 2 : 0);
     constexpr int NB = (S + (RESID ? 2 : 1) <= 3) ? 3 : 6;  // queue of b rows
     constexpr int CHUNK = NB;  // steps per block: a multiple of 3 and of NB
     Unit un;
     if (!unit_of(gr, un)) return;
     const int n = L.n;
-    const Lanes<T> ln = lanes_of(L, un.strip, OWN, HALO);
-    const int lane = (int)(threadIdx.x % WAVE);
-    const bool own = lane >= HALO && lane < HALO + OWN && ln.i <= n;
+    const Lanes<T> ln = lanes_of(L, un.strip, (int)gr.strips, HALO);
+    const bool own = ln.i >= ln.lo_own && ln.i < ln.hi_own;
     const int y0 = un.seg * gr.H;
     const int y1 = min(y0 + gr.H, n + 1);  // owned rows [y0, y1)
     const int jl = (y1 - 1) & ~1;          // last even owned row
@@ -321,19 +401,19 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     // one step of phase P: input row t, every stage one row on
     auto step = [&](auto pc, auto ec, const SweepIn<T, PROLONG, UPDATE>& in, int t) {
         constexpr int P = decltype(pc)::value;
-        constexpr bool EDGE = decltype(ec)::value;
+        constexpr int MODE = decltype(ec)::value;
         using Q = Slots<P>;
         cx<T> x0 = in.x;
         if (PROLONG) x0 = cfma(mk((T)0.5, (T)0), in.e0 + in.e1, x0);
-        ring_push<P>(rg[0], clip<EDGE>(x0, ln, t, n));
+        ring_push<P>(rg[0], clip<MODE>(x0, ln, t, n));
         bq[P % NB] = in.b;
 #pragma unroll
         for (int s = 1; s <= S; ++s) {
             const int r = t - s;
             const Ring<T>& g = rg[s - 1];
             const cx<T> br = bq[qslot<NB>(P, s)];
-            const cx<T> v = clip<EDGE>(
-                cfma(ring_jf<EDGE>(ln, r, n), br - ring_apply<P, EDGE>(L, g, ln, r), g.v[Q::C]), ln,
+            const cx<T> v = clip<MODE>(
+                cfma(ring_jf<MODE>(ln, r, n), br - ring_apply<P, MODE>(L, g, ln, r), g.v[Q::C]), ln,
                 r, n);
             if (s < S) {
                 ring_push<P>(rg[s], v);
@@ -343,14 +423,14 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
                     if (UPDATE) xo[gi] = in.u + v;
                     else xo[gi] = v;
                 }
-                if (RESID) ring_push<P>(rg[S], v);
+                if constexpr (RESID) ring_push<P>(rg[S], v);
             }
         }
-        if (RESID) {
+        if constexpr (RESID) {
             // residual of the final iterate, row t - S - 1
             const int r = t - S - 1;
-            const cx<T> rv = bq[qslot<NB>(P, S + 1)] - ring_apply<P, EDGE>(L, rg[S], ln, r);
-            ring_push<P>(rg[S + 1], clip<EDGE>(rv, ln, r, n));
+            const cx<T> rv = bq[qslot<NB>(P, S + 1)] - ring_apply<P, MODE>(L, rg[S], ln, r);
+            ring_push<P>(rg[S + 1], clip<MODE>(rv, ln, r, n));
             // restriction at the fine row t - S - 2 when it is even
             const int rr = t - S - 2;
             if (!(rr & 1) && rr >= y0 && rr < y1) {
@@ -363,28 +443,40 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     SweepIn<T, PROLONG, UPDATE> buf[3];
     load(buf[0], tb);
     load(buf[1], tb + 1);
-    auto march = [&](auto ec) {
-        auto block = [&](auto pc, int t) {
-            constexpr int P = decltype(pc)::value;
-            load(buf[(P + 2) % 3], t + P + 2);
-            step(pc, ec, buf[P % 3], t + P);
-        };
-        for (int t = tb; t <= te; t += CHUNK) {
-            block(Int<0>{}, t);
-            block(Int<1>{}, t);
-            block(Int<2>{}, t);
+    // blocks of CHUNK steps in mode MODE; the blocks whose stencil rows,
+    // t - DEPTH .. t + CHUNK - 1, reach row 0 or row n run with the row mode
+    // added, in loops of their own before and after the main loop
+    auto march = [&](auto mc) {
+        constexpr int MODE = decltype(mc)::value;
+        auto chunk = [&](auto ec, int t) {
+            auto block = [&](auto pc) {
+                constexpr int P = decltype(pc)::value;
+                load(buf[(P + 2) % 3], t + P + 2);
+                step(pc, ec, buf[P % 3], t + P);
+            };
+            block(Int<0>{});
+            block(Int<1>{});
+            block(Int<2>{});
             if constexpr (CHUNK == 6) {
-                block(Int<3>{}, t);
-                block(Int<4>{}, t);
-                block(Int<5>{}, t);
+                block(Int<3>{});
+                block(Int<4>{});
+                block(Int<5>{});
             }
-        }
+        };
+        int t = tb;
+        for (; t <= te && t - DEPTH <= 0; t += CHUNK) chunk(Int<MODE | TOUCH_ROW>{}, t);
+        for (; t <= te && t + CHUNK - 1 < n; t += CHUNK) chunk(Int<MODE>{}, t);
+        for (; t <= te; t += CHUNK) chunk(Int<MODE | TOUCH_ROW>{}, t);
     };
-    // a unit whose stencil rows (tb - DEPTH .. its last step) or columns
-    // include a mesh boundary runs the boundary-aware code
-    const int rlo = tb - DEPTH, rhi = tb + ((te - tb) / CHUNK + 1) * CHUNK - 1;
-    if (ln.any_colb || (rlo <= 0 && 0 <= rhi) || (rlo <= n && n <= rhi)) march(Bool<true>{});
-    else march(Bool<false>{});
+    // boundary columns are a property of the strip; boundary rows (and the
+    // rows outside the mesh) only concern the first and last blocks of steps
+    // of a segment that reaches them
+    if (ln.any_colb) {
+        if (n + 1 < WAVE) march(Int<TOUCH_COL | CLIP_LANES>{});
+        else march(Int<TOUCH_COL>{});
+    } else {
+        march(Int<0>{});
+    }
 }
 
 // ---- k_stream_pre -----------------------------------------------------------
@@ -404,13 +496,11 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     constexpr int DB = HSS == 1 ? 1 : 0;  // rows by which b lags the input
     constexpr int DEPTH = 3 + DB;
     constexpr int HALO = DEPTH;
-    constexpr int OWN = WAVE - 2 * HALO;
     Unit un;
     if (!unit_of(gr, un)) return;
     const int n = L.n;
-    const Lanes<T> ln = lanes_of(L, un.strip, OWN, HALO);
-    const int lane = (int)(threadIdx.x % WAVE);
-    const bool own = lane >= HALO && lane < HALO + OWN && ln.i <= n;
+    const Lanes<T> ln = lanes_of(L, un.strip, (int)gr.strips, HALO);
+    const bool own = ln.i >= ln.lo_own && ln.i < ln.hi_own;
     const int y0 = un.seg * gr.H;
     const int y1 = min(y0 + gr.H, n + 1);
     const int jl = (y1 - 1) & ~1;
@@ -442,14 +532,14 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
 
     auto step = [&](auto pc, auto ec, const PreIn<T>& in, int t) {
         constexpr int P = decltype(pc)::value;
-        constexpr bool EDGE = decltype(ec)::value;
+        constexpr int MODE = decltype(ec)::value;
         using Q = Slots<P>;
         cx<T> bnew;
         int rb;  // row of bnew
         if (HSS == 1) {
-            ring_push<P>(gu, clip<EDGE>(in.u, ln, t, n));
+            ring_push<P>(gu, clip<MODE>(in.u, ln, t, n));
             rb = t - 1;
-            bnew = c * (rq[(P + 1) % 2] - ring_apply<P, EDGE>(Bs, gu, ln, rb));
+            bnew = c * (rq[(P + 1) % 2] - ring_apply<P, MODE>(Bs, gu, ln, rb));
             rq[P % 2] = in.s;
         } else if (HSS == 2) {
             rb = t;
@@ -461,20 +551,20 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         if (HSS != 0 && own && rb >= y0 && rb < y1) rho[(long long)rb * np + ln.i] = bnew;
         bq[P % 3] = bnew;
         // first sweep (pointwise): row rb
-        ring_push<P>(g1, clip<EDGE>(ring_jf<EDGE>(ln, rb, n) * bnew, ln, rb, n));
+        ring_push<P>(g1, clip<MODE>(ring_jf<MODE>(ln, rb, n) * bnew, ln, rb, n));
         // second sweep: row rb - 1, written
         {
             const int r = rb - 1;
             const cx<T> v =
-                cfma(ring_jf<EDGE>(ln, r, n), bq[qslot<3>(P, 1)] - ring_apply<P, EDGE>(L, g1, ln, r),
+                cfma(ring_jf<MODE>(ln, r, n), bq[qslot<3>(P, 1)] - ring_apply<P, MODE>(L, g1, ln, r),
                      g1.v[Q::C]);
             if (own && r >= y0 && r < y1) x[(long long)r * np + ln.i] = v;
-            ring_push<P>(g2, clip<EDGE>(v, ln, r, n));
+            ring_push<P>(g2, clip<MODE>(v, ln, r, n));
         }
         // residual: row rb - 2
         {
             const int r = rb - 2;
-            ring_push<P>(gr3, clip<EDGE>(bq[qslot<3>(P, 2)] - ring_apply<P, EDGE>(L, g2, ln, r), ln, r, n));
+            ring_push<P>(gr3, clip<MODE>(bq[qslot<3>(P, 2)] - ring_apply<P, MODE>(L, g2, ln, r), ln, r, n));
         }
         // restriction at the fine row rb - 3 when even
         {
@@ -490,48 +580,69 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     PreIn<T> buf[3];
     load(buf[0], tb);
     load(buf[1], tb + 1);
-    auto march = [&](auto ec) {
-        auto block = [&](auto pc, int t) {
-            constexpr int P = decltype(pc)::value;
-            load(buf[(P + 2) % 3], t + P + 2);
-            step(pc, ec, buf[P % 3], t + P);
-        };
-        for (int t = tb; t <= te; t += CHUNK) {
-            block(Int<0>{}, t);
-            block(Int<1>{}, t);
-            block(Int<2>{}, t);
+    // blocks of CHUNK steps in mode MODE; the blocks whose stencil rows,
+    // t - DEPTH .. t + CHUNK - 1, reach row 0 or row n run with the row mode
+    // added, in loops of their own before and after the main loop
+    auto march = [&](auto mc) {
+        constexpr int MODE = decltype(mc)::value;
+        auto chunk = [&](auto ec, int t) {
+            auto block = [&](auto pc) {
+                constexpr int P = decltype(pc)::value;
+                load(buf[(P + 2) % 3], t + P + 2);
+                step(pc, ec, buf[P % 3], t + P);
+            };
+            block(Int<0>{});
+            block(Int<1>{});
+            block(Int<2>{});
             if constexpr (CHUNK == 6) {
-                block(Int<3>{}, t);
-                block(Int<4>{}, t);
-                block(Int<5>{}, t);
+                block(Int<3>{});
+                block(Int<4>{});
+                block(Int<5>{});
             }
-        }
+        };
+        int t = tb;
+        for (; t <= te && t - DEPTH <= 0; t += CHUNK) chunk(Int<MODE | TOUCH_ROW>{}, t);
+        for (; t <= te && t + CHUNK - 1 < n; t += CHUNK) chunk(Int<MODE>{}, t);
+        for (; t <= te; t += CHUNK) chunk(Int<MODE | TOUCH_ROW>{}, t);
     };
-    // a unit whose stencil rows (tb - DEPTH .. its last step) or columns
-    // include a mesh boundary runs the boundary-aware code
-    const int rlo = tb - DEPTH, rhi = tb + ((te - tb) / CHUNK + 1) * CHUNK - 1;
-    if (ln.any_colb || (rlo <= 0 && 0 <= rhi) || (rlo <= n && n <= rhi)) march(Bool<true>{});
-    else march(Bool<false>{});
+    // boundary columns are a property of the strip; boundary rows (and the
+    // rows outside the mesh) only concern the first and last blocks of steps
+    // of a segment that reaches them
+    if (ln.any_colb) {
+        if (n + 1 < WAVE) march(Int<TOUCH_COL | CLIP_LANES>{});
+        else march(Int<TOUCH_COL>{});
+    } else {
+        march(Int<0>{});
+    }
 }
 
 }  // namespace
 
 StreamGrid stream_grid(int n, int halo, int ns, int H) {
     StreamGrid g;
-    const int own = WAVE - 2 * halo;
     g.H = H;
-    g.strips = (unsigned)((n + 1 + own - 1) / own);
+    g.strips = (unsigned)strip_count(n, halo);
     g.segs = (unsigned)((n + 1 + H - 1) / H);
     g.units = g.strips * g.segs * (unsigned)ns;
+    const unsigned I = (g.strips > 2 && g.segs > 2) ? (g.strips - 2) * (g.segs - 2) : 0;
+    g.edge_units = (g.strips * g.segs - I) * (unsigned)ns;
+    // boundary workgroups, rounded up to whole rounds over the 8 XCDs
+    g.eblocks = (g.edge_units + SW - 1) / SW;
+    g.eblocks = (g.eblocks + 7) / 8 * 8;
     return g;
 }
 
-// Segment height.  A segment of H rows costs about H + 2 halo + 1 steps of
-// one wavefront; the kernel takes at least as long as one wavefront's chain
-// of steps (about 1.2 us per step) and as long as all wavefronts' steps at
-// the chip's throughput (about 1400 wavefront-steps per microsecond).  The
-// height minimising the larger of the two is used.
-static int stream_rows(int n, int halo, int ns) {
+// Segment height.  The kernel's time depends on the chain of steps of one
+// wavefront (H + 2 halo + 1), on how the units fill the wavefront slots and
+// on the slower boundary units; the best height is measured.  The first
+// time a configuration (kernel, mesh size, slot count, precision) is launched
+// on a stream that is not being captured, every candidate height is timed
+// on the real operands (all the kernels timed this way recompute the same
+// outputs from unchanged inputs) and the fastest is kept for the process.
+// Until then, and under capture, a model picks the height: the larger of one
+// wavefront's chain (about 1.2 us per step) and all wavefronts' steps at the
+// chip's throughput (about 1400 wavefront-steps per microsecond).
+static int stream_rows_model(int n, int halo, int ns) {
     int best = 64;
     double tbest = 1e30;
     for (int H = 4; H <= 128; H *= 2) {
@@ -546,7 +657,63 @@ static int stream_rows(int n, int halo, int ns) {
     return best;
 }
 
-static unsigned stream_blocks(const StreamGrid& g) { return (g.units + SW - 1) / SW; }
+static unsigned stream_blocks(const StreamGrid& g) {
+    return g.eblocks + (g.units - g.edge_units + SW - 1) / SW;
+}
+
+enum StreamKind : int { SK_S4R = 0, SK_S2P, SK_S2R, SK_S4P, SK_S1, SK_PRE0, SK_PRE1, SK_PRE2 };
+
+struct RowsKey {
+    int kind, n, ns, bytes;
+    bool operator<(const RowsKey& o) const {
+        return std::tie(kind, n, ns, bytes) < std::tie(o.kind, o.n, o.ns, o.bytes);
+    }
+};
+static std::mutex g_rows_mu;
+static std::map<RowsKey, int> g_rows;
+
+// Height for a launch of `kind`; `launch(H)` enqueues the kernel with height
+// H.  tune = false: only look up (the kernel is not safe to repeat).
+template <typename F>
+static int stream_rows(hipStream_t st, RowsKey key, int halo, bool tune, F launch) {
+    {
+        std::lock_guard<std::mutex> lk(g_rows_mu);
+        auto it = g_rows.find(key);
+        if (it != g_rows.end()) return it->second;
+    }
+    const int model = stream_rows_model(key.n, halo, key.ns);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!tune || hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return model;
+    static const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 42, 48, 56, 64, 96, 128};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return model;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return model;
+    }
+    int best = model;
+    float tbest = 1e30f;
+    for (int H : cand) {
+        if (H > key.n + 1 && H != 4) break;
+        launch(H);  // warm
+        (void)hipEventRecord(e0, st);
+        launch(H);
+        launch(H);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < tbest) {
+            tbest = ms;
+            best = H;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_rows_mu);
+    g_rows[key] = best;
+    return best;
+}
 
 template <typename T>
 void stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin,
@@ -554,17 +721,28 @@ void stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> X
                       bool update, int ns) {
     const bool pro = Ec.base != nullptr, resid = Bc.base != nullptr;
     const int halo = S + (resid ? 2 : 0);
-    const StreamGrid g = stream_grid(L.n, halo, ns, stream_rows(L.n, halo, ns));
-    const unsigned nb = stream_blocks(g);
+    int kind = -1;
+    if (S == 4 && pro && resid && !update) kind = SK_S4R;
+    else if (S == 2 && pro && !resid) kind = SK_S2P;  // the update variant shares its height
+    else if (S == 2 && !pro && resid && !update) kind = SK_S2R;
+    else if (S == 4 && pro && !resid && !update) kind = SK_S4P;
+    else if (S == 1 && !pro && !resid && !update) kind = SK_S1;
+    if (kind < 0) return;
+    auto launch = [&](int H) {
+        const StreamGrid g = stream_grid(L.n, halo, ns, H);
+        const unsigned nb = stream_blocks(g);
 #define HELM_STREAM(SS, PP, RR, UU) \
     k_stream_sweeps<T, SS, PP, RR, UU><<<nb, WAVE * SW, 0, st>>>(L, Xin, Ec, B, Xout, Bc, g)
-    if (S == 4 && pro && resid && !update) HELM_STREAM(4, true, true, false);
-    else if (S == 2 && pro && !resid && update) HELM_STREAM(2, true, false, true);
-    else if (S == 2 && pro && !resid && !update) HELM_STREAM(2, true, false, false);
-    else if (S == 2 && !pro && resid && !update) HELM_STREAM(2, false, true, false);
-    else if (S == 4 && pro && !resid && !update) HELM_STREAM(4, true, false, false);
-    else if (S == 1 && !pro && !resid && !update) HELM_STREAM(1, false, false, false);
+        if (kind == SK_S4R) HELM_STREAM(4, true, true, false);
+        else if (kind == SK_S2P && update) HELM_STREAM(2, true, false, true);
+        else if (kind == SK_S2P) HELM_STREAM(2, true, false, false);
+        else if (kind == SK_S2R) HELM_STREAM(2, false, true, false);
+        else if (kind == SK_S4P) HELM_STREAM(4, true, false, false);
+        else HELM_STREAM(1, false, false, false);
 #undef HELM_STREAM
+    };
+    // u += x is not safe to repeat: the update launch only looks up
+    launch(stream_rows(st, RowsKey{kind, L.n, ns, (int)sizeof(T)}, halo, !update, launch));
 }
 
 template <typename T>
@@ -573,14 +751,17 @@ void stream_pre_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<c
                    Vec<cx<T>> Bc, int ns) {
     const int hss = B.base ? 0 : (U.base ? 1 : 2);
     const int halo = 3 + (hss == 1 ? 1 : 0);
-    const StreamGrid g = stream_grid(L.n, halo, ns, stream_rows(L.n, halo, ns));
-    const unsigned nb = stream_blocks(g);
-    if (hss == 0)
-        k_stream_pre<T, 0><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
-    else if (hss == 1)
-        k_stream_pre<T, 1><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
-    else
-        k_stream_pre<T, 2><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
+    auto launch = [&](int H) {
+        const StreamGrid g = stream_grid(L.n, halo, ns, H);
+        const unsigned nb = stream_blocks(g);
+        if (hss == 0)
+            k_stream_pre<T, 0><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
+        else if (hss == 1)
+            k_stream_pre<T, 1><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
+        else
+            k_stream_pre<T, 2><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
+    };
+    launch(stream_rows(st, RowsKey{SK_PRE0 + hss, L.n, ns, (int)sizeof(T)}, halo, true, launch));
 }
 
 template void stream_sweeps_2d<double>(hipStream_t, const Op2<double>&, int, Vec<const cxd>,

@@ -50,10 +50,12 @@ void hss_pre0r_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<co
 
 // ---- register-streaming 2D kernels (kernels2d_stream.hip) -----------------
 // Work split: strips of 64 columns (one per lane) x segments of H rows x
-// slots; one wavefront per unit.
+// slots; one wavefront per unit.  The units on the mesh boundary (first and
+// last strip or segment) form the first `eblocks` workgroups.
 struct StreamGrid {
     int H;
     unsigned strips, segs, units;
+    unsigned edge_units, eblocks;
 };
 StreamGrid stream_grid(int n, int halo, int ns, int H);
 // x_out = S Jacobi sweeps from x_in (+ P e_c when Ec.base is set); with

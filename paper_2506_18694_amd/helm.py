@@ -53,7 +53,7 @@ class helm_opts(ctypes.Structure):
                 ("profile", ctypes.c_int), ("mg_cycles", ctypes.c_int),
                 ("no_graphs", ctypes.c_int), ("no_small", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("no_stream", ctypes.c_int),
-                ("no_split", ctypes.c_int)]
+                ("split", ctypes.c_int)]
 
 
 class helm_stats(ctypes.Structure):
@@ -162,7 +162,7 @@ class Solver:
     def __init__(self, dim, n, levels, k, delta=0.0, delta_hat=None, precision="fp64",
                  restart=0, max_outer=0, hss_steps=0, hss_m=1, omega=2.0 / 3.0,
                  dirichlet_faces=0, profile=False, mg_cycles=0, graphs=True, small_kernel=True,
-                 verbose=0, stream=None, streaming=True, split=True):
+                 verbose=0, stream=None, streaming=True, split=False):
         import torch
         self.torch = torch
         L = lib()
@@ -178,7 +178,7 @@ class Solver:
         opts.no_small = 0 if small_kernel else 1
         opts.verbose = int(verbose)
         opts.no_stream = 0 if streaming else 1
-        opts.no_split = 0 if split else 1
+        opts.split = 1 if split else 0
         bc = helm_bc(dirichlet_faces)
         if stream is None:
             stream = torch.cuda.current_stream()

@@ -5,7 +5,8 @@ GPU result is compared with the oracle's direct solve: relative l2 error
 <= 1e-6 for the FP64 path and <= 1e-5 for the FP32-multigrid path at the
 1e-8 residual tolerance, and the true residual is recomputed with the
 oracle's assembled CSR B_0.  Iteration counts are not unique (rounding,
-CGS2 vs MGS) and must agree with the oracle's FGMRES within +-1.
+CGS2 vs MGS) and must agree with the oracle's FGMRES within +-1 (FP64
+path) or +-2 (FP32-multigrid path).
 """
 
 import numpy as np
@@ -44,7 +45,12 @@ def test_small_workload(small, prec, tol_err):
     assert rel_l2(x, u) < tol_err
     r = np.linalg.norm(b[0] - pr.B0 @ x[0]) / np.linalg.norm(b[0])
     assert r <= 1e-8 * 1.01
-    assert abs(st["outer_its"] - oracle_its) <= 1, (st["outer_its"], oracle_its)
+    # FP64: the same preconditioner up to summation order.  FP32-MG: every
+    # inner solve carries rounding of relative size ~1e-7, a perturbation of
+    # the preconditioner that flexible GMRES absorbs at the cost of an extra
+    # iteration or two near the 1e-8 tolerance.
+    slack = 1 if prec == "fp64" else 2
+    assert abs(st["outer_its"] - oracle_its) <= slack, (st["outer_its"], oracle_its)
     assert st["hss_steps"] == 10
 
 
@@ -86,6 +92,30 @@ def test_3d_small_solve():
         x, st = s.solve(to_dev(b), tol=1e-8)
         assert st["converged"] == 1
         assert rel_l2(to_host(x)[0], u) < tol
+
+
+def test_profiled_solve_times_graph_launches():
+    """Timing the finest-level four-sweep passes (event nodes inside the
+    captured graphs, or event records between eager launches) changes no
+    result; every timed launch moves 3.5 vectors per right-hand side."""
+    n, k, levels = 64, 10.0, 3
+    pr = osolver.Problem(2, n, k, k, levels=levels)
+    b = (pr.M @ W.gaussian_nodal(2, n, (0.5, 0.5), 0.05))[None]
+    for graphs in (True, False):
+        out = {}
+        for prof in (False, True):
+            s = _solver(2, n, levels, k, profile=prof, graphs=graphs, mg_cycles=3)
+            x, st = s.solve(to_dev(b), tol=1e-8)
+            out[prof] = (to_host(x), st)
+            s.close()
+        assert np.array_equal(out[True][0], out[False][0])
+        assert out[False][1]["sweep_launches"] == 0
+        st = out[True][1]
+        # two timed four-sweep passes per HSS step (three cycles)
+        assert st["sweep_launches"] >= 2 * st["hss_steps"] * st["outer_its"]
+        assert st["sweep_ms"] > 0
+        assert st["sweep_bytes"] / st["sweep_launches"] == pytest.approx(3.5 * 16 * (n + 1) ** 2,
+                                                                          rel=1e-12)
 
 
 def test_no_convergence_reports_enoconv():
