@@ -269,7 +269,11 @@ def main():
                       "vcycle_rate": r["stats"][0]["vcycle_rate"],
                       "true_rel_residual": max(st["true_rel_residual"] for st in r["stats"]),
                       "converged": r["ok"]},
-           "roofline": roof}
+           "roofline": roof,
+           # where a solve's time goes: device time inside the preconditioner
+           # (HSS loop) against the whole solve's wall time
+           "breakdown": {"solve_ms": sum(st["solve_ms"] for st in r["stats"]) / len(r["stats"]),
+                         "precond_ms": sum(st["precond_ms"] for st in r["stats"]) / len(r["stats"])}}
     if not args.no_fp32 and main_prec == "fp64":
         r32 = run_solves(W, name, "fp32", 1, 1, args.tol, streaming=not args.lds_kernels,
                          split=args.split)

@@ -131,6 +131,12 @@ typedef struct {
                           streaming kernels (one wavefront marches up a
                           strip of 64 columns, every sweep a pipeline stage
                           one row behind the previous one)                   */
+    int    full_reorth; /* 1: classical Gram-Schmidt twice at every Arnoldi
+                          step; by default the second pass runs only for
+                          the columns whose first pass kept less than
+                          1/sqrt(2) of the new vector's norm (Kahan's
+                          criterion; estimated as |w|^2 - |h|^2 on the
+                          device, no host synchronisation)                  */
     int    split;      /* 1: with two or more columns, split them into two
                           groups whose HSS loops run on two streams (one
                           group's finest-level passes can overlap the
@@ -160,6 +166,8 @@ typedef struct {
     int    mg_cycles;            /* V-cycles per inner HSS solve used          */
     double vcycle_rate;          /* measured V-cycle contraction (automatic
                                     mode; 0 when mg_cycles was given)         */
+    long long reorth_passes;     /* second Gram-Schmidt passes run, summed
+                                    over columns and iterations               */
 } helm_stats;
 
 /* Fill *opts with the defaults listed above. */

@@ -10,8 +10,9 @@
 //      V[c][0] = r / beta; columns waiting for their final check: |b - B X|;
 //   2. all iterating columns: z = B~^{-1} V[c][j] (the shifted-HSS
 //      preconditioner, one batched launch sequence), w = B z, classical
-//      Gram-Schmidt twice against V[c][0..j], h_{j+1,j} = |w|,
-//      V[c][j+1] = w / h_{j+1,j};
+//      Gram-Schmidt against V[c][0..j], repeated once for the columns whose
+//      first pass cancelled most of w (Kahan's "twice is enough" test,
+//      taken on the device), h_{j+1,j} = |w|, V[c][j+1] = w / h_{j+1,j};
 //   3. one device->host copy of the new Hessenberg columns and norms.
 // The host then applies the Givens rotations per column and decides:
 // converged or out of iterations -> X[c] += Z[c] y and a true-residual
@@ -47,13 +48,14 @@ struct Engine {
     int* hfin = nullptr;     // NMAPS * cap (finishing maps)
     cxd* hh = nullptr;       // 2 * cap * (R + 1)
     double* hn = nullptr;    // 3 * cap
+    int* hflag = nullptr;    // cap (second Gram-Schmidt pass taken)
     cxd* hy = nullptr;       // cap * R
     hipEvent_t ev = nullptr;
     // the last enqueued step
     std::vector<int> it_cols, chk_cols, fresh_cols;
     bool pending = false;
     double precond_ms = 0.0;
-    long long vcycles = 0;
+    long long vcycles = 0, reorth = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
 
     // device views
@@ -63,6 +65,7 @@ struct Engine {
     double* d_norm() const { return reinterpret_cast<double*>(ws + Lw.dnorm); }
     cxd* d_part() const { return reinterpret_cast<cxd*>(ws + Lw.part); }
     double* d_npart() const { return reinterpret_cast<double*>(ws + Lw.npart); }
+    int* d_flag() const { return reinterpret_cast<int*>(ws + Lw.flag); }
     cxd* d_y() const { return reinterpret_cast<cxd*>(ws + Lw.dy); }
     cxd* Vb() const { return reinterpret_cast<cxd*>(ws + Lw.V); }
     cx<T>* Zb() const { return reinterpret_cast<cx<T>*>(ws + Lw.Z); }
@@ -83,6 +86,7 @@ struct Engine {
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hfin), sizeof(int) * NMAPS * cap, 0));
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hh), sizeof(cxd) * 2 * cap * (R + 1), 0));
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hn), sizeof(double) * 3 * cap, 0));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hflag), sizeof(int) * cap, 0));
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hy), sizeof(cxd) * (size_t)cap * R, 0));
         HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         HIPCHK(hipEventCreate(&e0));
@@ -93,6 +97,7 @@ struct Engine {
         if (hfin) (void)hipHostFree(hfin);
         if (hh) (void)hipHostFree(hh);
         if (hn) (void)hipHostFree(hn);
+        if (hflag) (void)hipHostFree(hflag);
         if (hy) (void)hipHostFree(hy);
         if (ev) (void)hipEventDestroy(ev);
         if (e0) (void)hipEventDestroy(e0);
@@ -222,12 +227,22 @@ struct Engine {
             const Vec<const cxd> V0{Vb(), N, 0, dm + 5 * cap};
             const Vec<cxd> W{Vb(), N, 0, dm + 4 * cap};
             const int nblk = multidot_blocks(N);
+            // classical Gram-Schmidt; the second pass runs for the columns
+            // whose first pass cancelled more than 1/sqrt(2) of w's norm
+            // (every column with full_reorth), decided on the device
+            const bool sel = !h->opts.full_reorth;
+            const int* flag2 = sel ? d_flag() : nullptr;
             for (int pass = 0; pass < 2; ++pass) {
                 cxd* hd = pass == 0 ? d_h() : d_h2();
-                multidot(s, N, jmax, dm + 7 * cap, V0, cst(W), d_part(), ni);
-                reduce_parts(s, jmax, dm + 7 * cap, nblk, d_part(), hd, R + 1, 0, ni);
-                multi_axpy(s, N, jmax, dm + 7 * cap, V0, hd, R + 1, W, ni);
+                multidot(s, N, jmax, dm + 7 * cap, V0, cst(W), d_part(), ni,
+                         pass == 0 && sel ? d_npart() : nullptr, pass == 1 ? flag2 : nullptr);
+                reduce_parts(s, jmax, dm + 7 * cap, nblk, d_part(), hd, R + 1, 0, ni,
+                             pass == 1 ? flag2 : nullptr);
+                if (pass == 0 && sel)
+                    reorth_flag(s, jmax, dm + 7 * cap, nblk, d_npart(), hd, R + 1, d_flag(), ni);
+                multi_axpy(s, N, jmax, dm + 7 * cap, V0, hd, R + 1, W, ni, pass == 1 ? flag2 : nullptr);
             }
+            if (sel) HIPCHK(hipMemcpyAsync(hflag, d_flag(), sizeof(int) * ni, hipMemcpyDeviceToHost, s));
             norm2(s, N, cst(W), d_npart(), dn, 1, ni);
             scale_inv(s, N, cst(W), W, dn, 1, ni);
             HIPCHK(hipMemcpyAsync(hh, d_h(), sizeof(cxd) * ni * (R + 1), hipMemcpyDeviceToHost, s));
@@ -249,6 +264,7 @@ struct Engine {
         if (!it_cols.empty()) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) precond_ms += ms;
+            for (size_t q = 0; q < it_cols.size(); ++q) reorth += h->opts.full_reorth ? 1 : hflag[q];
         }
         if (h->prof_on) h->prof_collect();
         // b norms of fresh columns

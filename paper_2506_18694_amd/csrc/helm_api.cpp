@@ -256,7 +256,7 @@ struct Layout {
     size_t mg_b[32], mg_x[32], mg_t[32];
     size_t R, u;
     size_t V, Z, Bw, Xw;
-    size_t dh, dh2, dnorm, part, npart, dy, cols, maps;
+    size_t dh, dh2, dnorm, part, npart, dy, cols, maps, flag;
     size_t total;
 };
 
@@ -274,6 +274,7 @@ Layout layout(const helm_t* h, int nrhs) {
     const int nblk = multidot_blocks(N);
     L.cols = take(sizeof(int) * nrhs);
     L.maps = take(sizeof(int) * NMAPS * nrhs);
+    L.flag = take(sizeof(int) * nrhs);
     L.dh = take(sizeof(cxd) * nrhs * (R + 1));
     L.dh2 = take(sizeof(cxd) * nrhs * (R + 1));
     L.dnorm = take(sizeof(double) * 3 * nrhs);
@@ -418,7 +419,11 @@ void run_small(helm_t* h, int l0, Vec<const cx<T>> b, Vec<cx<T>> x, int ns) {
     // shared scratch: the largest level's vector, and room for 1024 FP64
     // complex partial sums of the coarse solve; 16-byte aligned
     off += off & 1;
-    for (int m = 0; m < sc.nlev; ++m) sc.off_t[m] = off;
+    for (int m = 0; m < sc.nlev; ++m) {
+        sc.off_t[m] = off;
+        sc.mdiv[m] = ((1 << 20) + h->nl[l0 + m]) / (h->nl[l0 + m] + 1);
+    }
+    sc.off_part = off;
     off += std::max((int)h->Nl[l0], 1024 * (int)(sizeof(cxd) / sizeof(cx<T>)));
     vcycle_small<T>(h->stream, sc, sizeof(cx<T>) * (size_t)off, h->d_cinv, h->nc, b, x, ns);
 }
@@ -801,6 +806,7 @@ int solve_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void*
         st->sweep_bytes = h->prof_bytes;
         st->mg_cycles = h->cycles;
         st->vcycle_rate = h->vrate;
+        st->reorth_passes = E.reorth;
     }
     return ok ? HELM_OK : HELM_ENOCONV;
 }
@@ -829,6 +835,7 @@ void helm_opts_default(helm_opts* o) {
     o->no_small = 0;
     o->verbose = 0;
     o->no_stream = 0;
+    o->full_reorth = 0;
     o->split = 0;
 }
 

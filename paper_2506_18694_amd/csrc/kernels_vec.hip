@@ -103,13 +103,16 @@ __global__ __launch_bounds__(BS) void k_real_to_complex(long long N, const doubl
 }
 
 // ---- Arnoldi reductions -------------------------------------------------------
-// part[(slot * m + i) * nblk + blk] = sum over the block's nodes of conj(V_i) w
+// part[(slot * m + i) * nblk + blk] = sum over the block's nodes of conj(V_i) w;
+// with wpart, also wpart[slot * nblk + blk] = the block's sum of |w|^2; with
+// flag, slots whose flag is 0 are skipped
 __global__ __launch_bounds__(BS) void k_multidot(long long N, int m, const int* mlen,
                                                  Vec<const cxd> V, Vec<const cxd> W, cxd* part,
-                                                 unsigned nblk) {
+                                                 unsigned nblk, double* wpart, const int* flag) {
     __shared__ double lds[(BS / WAVE) * 2 * GROUP];
     const int slot = blockIdx.x / nblk;
     const unsigned blk = blockIdx.x % nblk;
+    if (flag && !flag[slot]) return;  // uniform over the block
     const long long base = (long long)blk * BS * NPT + threadIdx.x;
     const cxd* w = W.at(slot);
     const cxd* v0 = V.at(slot);
@@ -147,15 +150,47 @@ __global__ __launch_bounds__(BS) void k_multidot(long long N, int m, const int* 
                     part[((long long)slot * m + i0 + u) * nblk + blk] = mk(acc[2 * u], acc[2 * u + 1]);
         }
     }
+    if (wpart) {
+        double acc[1] = {0.0};
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) acc[0] += wv[q].x * wv[q].x + wv[q].y * wv[q].y;
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) wpart[(long long)slot * nblk + blk] = acc[0];
+    }
 }
 
-// one block per (slot, i): out = sum over blocks, fixed order
+// Second classical Gram-Schmidt pass needed?  With h = V^H w from the first
+// pass and V orthonormal, |w - V h|^2 = |w|^2 - |h|^2; the pass is repeated
+// when that is below |w|^2 / 2 (the first pass cancelled more than a factor
+// 1/sqrt(2) of w's norm), and also when the sums are not finite.
+__global__ __launch_bounds__(BS) void k_reorth_flag(int m, const int* mlen, int nblk,
+                                                    const double* wpart, const cxd* h, int hstride,
+                                                    int* flag) {
+    __shared__ double lds[(BS / WAVE) * 2];
+    const int slot = blockIdx.x;
+    const int ms = mlen ? mlen[slot] : m;
+    double acc[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += BS) acc[0] += wpart[(long long)slot * nblk + b];
+    for (int i = threadIdx.x; i < ms; i += BS) {
+        const cxd v = h[(long long)slot * hstride + i];
+        acc[1] += v.x * v.x + v.y * v.y;
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) flag[slot] = (acc[1] <= 0.5 * acc[0]) ? 0 : 1;
+}
+
+// one block per (slot, i): out = sum over blocks, fixed order; with flag,
+// slots whose flag is 0 get out = 0 (or keep out when accumulating)
 __global__ __launch_bounds__(BS) void k_reduce_parts(int m, const int* mlen, int nblk,
                                                      const cxd* part, cxd* out, int ostride,
-                                                     int accumulate) {
+                                                     int accumulate, const int* flag) {
     __shared__ double lds[(BS / WAVE) * 2];
     const int slot = blockIdx.x / m, i = blockIdx.x % m;
     if (mlen && i >= mlen[slot]) return;  // uniform over the block
+    if (flag && !flag[slot]) {
+        if (threadIdx.x == 0 && !accumulate) out[(long long)slot * ostride + i] = mk(0.0, 0.0);
+        return;
+    }
     const cxd* p = part + ((long long)slot * m + i) * nblk;
     double acc[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < nblk; b += BS) {
@@ -200,12 +235,14 @@ __global__ __launch_bounds__(BS) void k_norm2_final(int nblk, const double* part
     if (threadIdx.x == 0) out[(long long)slot * ostride] = sqrt(acc[0]);
 }
 
-// w -= sum_i h_i V_i   (h from device memory, staged in LDS)
+// w -= sum_i h_i V_i   (h from device memory, staged in LDS); with flag,
+// slots whose flag is 0 are skipped
 __global__ __launch_bounds__(BS) void k_multi_axpy(long long N, int m, const int* mlen,
                                                    Vec<const cxd> V, const cxd* h, int hstride,
-                                                   Vec<cxd> W, unsigned gx) {
+                                                   Vec<cxd> W, unsigned gx, const int* flag) {
     extern __shared__ cxd hs[];
     const int slot = blockIdx.x / gx;
+    if (flag && !flag[slot]) return;  // uniform over the block
     const int ms = mlen ? mlen[slot] : m;
     for (int i = threadIdx.x; i < ms; i += BS) hs[i] = h[(long long)slot * hstride + i];
     __syncthreads();
@@ -273,20 +310,25 @@ void real_to_complex(hipStream_t st, long long N, const double* f, cxd* b, int n
 }
 
 void multidot(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
-              Vec<const cxd> W, cxd* part, int nslots) {
+              Vec<const cxd> W, cxd* part, int nslots, double* wpart, const int* flag) {
     const unsigned nblk = multidot_blocks(N);
-    k_multidot<<<nblk * nslots, BS, 0, st>>>(N, m, mlen, V, W, part, nblk);
+    k_multidot<<<nblk * nslots, BS, 0, st>>>(N, m, mlen, V, W, part, nblk, wpart, flag);
 }
 
 void reduce_parts(hipStream_t st, int m, const int* mlen, int nblk, const cxd* part, cxd* out,
-                  int ostride, int accumulate, int nslots) {
-    k_reduce_parts<<<m * nslots, BS, 0, st>>>(m, mlen, nblk, part, out, ostride, accumulate);
+                  int ostride, int accumulate, int nslots, const int* flag) {
+    k_reduce_parts<<<m * nslots, BS, 0, st>>>(m, mlen, nblk, part, out, ostride, accumulate, flag);
+}
+
+void reorth_flag(hipStream_t st, int m, const int* mlen, int nblk, const double* wpart,
+                 const cxd* h, int hstride, int* flag, int nslots) {
+    k_reorth_flag<<<nslots, BS, 0, st>>>(m, mlen, nblk, wpart, h, hstride, flag);
 }
 
 void multi_axpy(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
-                const cxd* h, int hstride, Vec<cxd> W, int nslots) {
+                const cxd* h, int hstride, Vec<cxd> W, int nslots, const int* flag) {
     const unsigned gx = blocks(N);
-    k_multi_axpy<<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, mlen, V, h, hstride, W, gx);
+    k_multi_axpy<<<gx * nslots, BS, sizeof(cxd) * m, st>>>(N, m, mlen, V, h, hstride, W, gx, flag);
 }
 
 void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* out, int ostride,

@@ -77,7 +77,9 @@ void stream_pre_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<c
 // ---- small-level V-cycle in LDS (kernels2d_small.hip) ---------------------
 // Levels 0..nlev-1 of this record are consecutive mesh levels; the last is
 // the coarsest (solved with the dense FP64 inverse).  Offsets are in
-// complex elements of the dynamic LDS arena; t is shared by all levels.
+// complex elements of the dynamic LDS arena; t is shared by all levels and
+// also holds the coarse solve's FP64 partial sums (off_part).  mdiv[l] =
+// ceil(2^20 / (n[l] + 1)) turns a node index into its row by a multiply.
 constexpr int MAX_SMALL = 8;
 template <typename T>
 struct SmallCycle {
@@ -85,6 +87,8 @@ struct SmallCycle {
     int n[MAX_SMALL];
     Op2<T> op[MAX_SMALL];
     int off_b[MAX_SMALL], off_x[MAX_SMALL], off_t[MAX_SMALL];
+    int mdiv[MAX_SMALL];
+    int off_part;
 };
 template <typename T>
 void vcycle_small(hipStream_t st, const SmallCycle<T>& sc, size_t lds_bytes, const cxd* Ainv,
@@ -116,15 +120,23 @@ void scale_inv(hipStream_t st, long long N, Vec<const cxd> X, Vec<cxd> Y, const 
 // partial dot products: part[slot][i][blk] = sum_{n in blk} conj(V_i[n]) w[n], i < m
 // V_i at Vb.at(slot) + i*N
 int multidot_blocks(long long N);
-// mlen (nullable, device): per-slot vector count <= m; m sets the layout
+// mlen (nullable, device): per-slot vector count <= m; m sets the layout.
+// wpart (nullable): also wpart[slot][blk] = sum_{n in blk} |w[n]|^2.
+// flag (nullable, device): slots with flag[slot] == 0 are skipped.
 void multidot(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
-              Vec<const cxd> W, cxd* part, int nslots);
-// reduce part over blocks: out[slot*ostride + i] (+)= sum_blk part[slot][i][blk]
+              Vec<const cxd> W, cxd* part, int nslots, double* wpart = nullptr,
+              const int* flag = nullptr);
+// reduce part over blocks: out[slot*ostride + i] (+)= sum_blk part[slot][i][blk];
+// slots with flag[slot] == 0 get 0 (or keep out when accumulating)
 void reduce_parts(hipStream_t st, int m, const int* mlen, int nblk, const cxd* part, cxd* out,
-                  int ostride, int accumulate, int nslots);
-// w -= sum_{i<m} h[slot*hstride + i] V_i
+                  int ostride, int accumulate, int nslots, const int* flag = nullptr);
+// flag[slot] = 1 when |w|^2 - |h|^2 < |w|^2 / 2 (|w|^2 from multidot's wpart,
+// h the first Gram-Schmidt pass's coefficients), else 0
+void reorth_flag(hipStream_t st, int m, const int* mlen, int nblk, const double* wpart,
+                 const cxd* h, int hstride, int* flag, int nslots);
+// w -= sum_{i<m} h[slot*hstride + i] V_i; slots with flag[slot] == 0 skipped
 void multi_axpy(hipStream_t st, long long N, int m, const int* mlen, Vec<const cxd> V,
-                const cxd* h, int hstride, Vec<cxd> W, int nslots);
+                const cxd* h, int hstride, Vec<cxd> W, int nslots, const int* flag = nullptr);
 // squared norm partials: part[slot][blk] = sum |w|^2 ; reduced into out[slot*ostride]
 void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* out, int ostride,
            int nslots);

@@ -53,7 +53,7 @@ class helm_opts(ctypes.Structure):
                 ("profile", ctypes.c_int), ("mg_cycles", ctypes.c_int),
                 ("no_graphs", ctypes.c_int), ("no_small", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("no_stream", ctypes.c_int),
-                ("split", ctypes.c_int)]
+                ("full_reorth", ctypes.c_int), ("split", ctypes.c_int)]
 
 
 class helm_stats(ctypes.Structure):
@@ -63,7 +63,8 @@ class helm_stats(ctypes.Structure):
                 ("true_rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double),
                 ("precond_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double),
                 ("sweep_launches", ctypes.c_longlong), ("sweep_bytes", ctypes.c_double),
-                ("mg_cycles", ctypes.c_int), ("vcycle_rate", ctypes.c_double)]
+                ("mg_cycles", ctypes.c_int), ("vcycle_rate", ctypes.c_double),
+                ("reorth_passes", ctypes.c_longlong)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -162,7 +163,8 @@ class Solver:
     def __init__(self, dim, n, levels, k, delta=0.0, delta_hat=None, precision="fp64",
                  restart=0, max_outer=0, hss_steps=0, hss_m=1, omega=2.0 / 3.0,
                  dirichlet_faces=0, profile=False, mg_cycles=0, graphs=True, small_kernel=True,
-                 verbose=0, stream=None, streaming=True, split=False):
+                 verbose=0, stream=None, streaming=True, split=False,
+                 full_reorth=False):
         import torch
         self.torch = torch
         L = lib()
@@ -179,6 +181,7 @@ class Solver:
         opts.verbose = int(verbose)
         opts.no_stream = 0 if streaming else 1
         opts.split = 1 if split else 0
+        opts.full_reorth = 1 if full_reorth else 0
         bc = helm_bc(dirichlet_faces)
         if stream is None:
             stream = torch.cuda.current_stream()

@@ -118,6 +118,31 @@ def test_profiled_solve_times_graph_launches():
                                                                           rel=1e-12)
 
 
+def test_selective_reorthogonalization_matches_full():
+    """The second Gram-Schmidt pass taken only where the first cancelled
+    more than 1/sqrt(2) of the new vector gives the same solution and
+    iteration count (+-1) as always taking it, and saves passes."""
+    n, k, levels = 64, 10.0, 3
+    pr = osolver.Problem(2, n, k, k, levels=levels)
+    centres = W.seeded_centres(3, 2, 5)
+    b = np.stack([pr.M @ W.gaussian_nodal(2, n, c, 0.05) for c in centres])
+    res = {}
+    for full in (False, True):
+        s = _solver(2, n, levels, k, full_reorth=full)
+        x, st = s.solve(to_dev(b), tol=1e-10)
+        res[full] = (to_host(x), st)
+        s.close()
+    for c in range(3):
+        u = pr.solve_direct(b[c])
+        assert rel_l2(res[False][0][c], u) < 1e-8
+        assert rel_l2(res[True][0][c], u) < 1e-8
+    sel, full = res[False][1], res[True][1]
+    assert sel["converged"] == 1 and full["converged"] == 1
+    assert abs(sel["outer_its"] - full["outer_its"]) <= 1
+    assert 0 <= sel["reorth_passes"] <= full["reorth_passes"]
+    assert full["reorth_passes"] >= full["outer_its"]
+
+
 def test_no_convergence_reports_enoconv():
     n, k, levels = 64, 10.0, 3
     pr = osolver.Problem(2, n, k, k, levels=levels)
