@@ -27,11 +27,11 @@
 // written.
 //
 // The march runs in unrolled blocks of steps: within a block the three-row
-// rings, the queue of right-hand-side rows and three input buffers rotate
-// by renaming registers (the block length is a multiple of every period),
-// and the input row t + 2 is loaded while step t computes.  A segment's
-// step count is rounded up to whole blocks; the extra steps compute rows
-// past the segment, which are never written.
+// rings, the queue of right-hand-side rows and the input buffers rotate by
+// renaming registers (the block length is a multiple of every period), and
+// the input row t + 2 is loaded while step t computes.  A segment's step
+// count is rounded up to whole blocks; the extra steps compute rows past
+// the segment, which are never written.
 //
 // The rows next to a segment's ends run through code with the boundary
 // handling compiled in, the others through code without it, and where
@@ -264,7 +264,7 @@ template <int P, typename T>
 __device__ __forceinline__ cx<T> ring_restrict(const Ring<T>& g) {
     using Q = Slots<P>;
     const cx<T> s6 = ((g.e[Q::C] + g.w[Q::C]) + (g.v[Q::N] + g.v[Q::O])) + (g.e[Q::N] + g.w[Q::O]);
-    return cfma(mk((T)0.5, (T)0), s6, g.v[Q::C]);
+    return axpy_real((T)0.5, s6, g.v[Q::C]);
 }
 
 // in a boundary unit: zero outside the mesh (row r uniform)
@@ -357,12 +357,14 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     constexpr int HALO = DEPTH;
     constexpr int NR = S + (RESID ? 2 : 0);
     constexpr int NB = (S + (RESID ? 2 : 1) <= 3) ? 3 : 6;  // queue of b rows
-    constexpr int CHUNK = NB;  // steps per block: a multiple of 3 and of NB
+    constexpr int NBUF = 3;    // input rows in flight
+    constexpr int CHUNK = NB;  // steps per block: a multiple of 3, NB and NBUF
     Unit un;
     if (!unit_of(gr, un)) return;
     const int n = L.n;
     const Lanes<T> ln = lanes_of(L, un.strip, (int)gr.strips, HALO);
     const bool own = ln.i >= ln.lo_own && ln.i < ln.hi_own;
+    [[maybe_unused]] const bool own_even = own & !(ln.i & 1);  // owned even column (coarse node)
     const int y0 = un.seg * gr.H;
     const int y1 = min(y0 + gr.H, n + 1);  // owned rows [y0, y1)
     const int jl = (y1 - 1) & ~1;          // last even owned row
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         constexpr int MODE = decltype(ec)::value;
         using Q = Slots<P>;
         cx<T> x0 = in.x;
-        if (PROLONG) x0 = cfma(mk((T)0.5, (T)0), in.e0 + in.e1, x0);
+        if (PROLONG) x0 = axpy_real((T)0.5, in.e0 + in.e1, x0);
         ring_push<P>(rg[0], clip<MODE>(x0, ln, t, n));
         bq[P % NB] = in.b;
 #pragma unroll
@@ -418,11 +420,7 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
             if (s < S) {
                 ring_push<P>(rg[s], v);
             } else {
-                if (own && r >= y0 && r < y1) {
-                    const long long gi = (long long)r * np + ln.i;
-                    if (UPDATE) xo[gi] = in.u + v;
-                    else xo[gi] = v;
-                }
+                if (own & (r >= y0) & (r < y1)) xo[(long long)r * np + ln.i] = UPDATE ? in.u + v : v;
                 if constexpr (RESID) ring_push<P>(rg[S], v);
             }
         }
@@ -433,16 +431,16 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
             ring_push<P>(rg[S + 1], clip<MODE>(rv, ln, r, n));
             // restriction at the fine row t - S - 2 when it is even
             const int rr = t - S - 2;
-            if (!(rr & 1) && rr >= y0 && rr < y1) {
+            if (!(rr & 1) & (rr >= y0) & (rr < y1)) {
                 const cx<T> v = ring_restrict<P>(rg[S + 1]);
-                if (own && !(ln.i & 1)) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
+                if (own_even) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
             }
         }
     };
 
-    SweepIn<T, PROLONG, UPDATE> buf[3];
-    load(buf[0], tb);
-    load(buf[1], tb + 1);
+    SweepIn<T, PROLONG, UPDATE> buf[NBUF];
+#pragma unroll
+    for (int k = 0; k < NBUF - 1; ++k) load(buf[k], tb + k);
     // blocks of CHUNK steps in mode MODE; the blocks whose stencil rows,
     // t - DEPTH .. t + CHUNK - 1, reach row 0 or row n run with the row mode
     // added, in loops of their own before and after the main loop
@@ -451,8 +449,8 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         auto chunk = [&](auto ec, int t) {
             auto block = [&](auto pc) {
                 constexpr int P = decltype(pc)::value;
-                load(buf[(P + 2) % 3], t + P + 2);
-                step(pc, ec, buf[P % 3], t + P);
+                load(buf[(P + NBUF - 1) % NBUF], t + P + NBUF - 1);
+                step(pc, ec, buf[P % NBUF], t + P);
             };
             block(Int<0>{});
             block(Int<1>{});
@@ -501,6 +499,7 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     const int n = L.n;
     const Lanes<T> ln = lanes_of(L, un.strip, (int)gr.strips, HALO);
     const bool own = ln.i >= ln.lo_own && ln.i < ln.hi_own;
+    [[maybe_unused]] const bool own_even = own & !(ln.i & 1);  // owned even column (coarse node)
     const int y0 = un.seg * gr.H;
     const int y1 = min(y0 + gr.H, n + 1);
     const int jl = (y1 - 1) & ~1;
@@ -548,7 +547,7 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
             rb = t;
             bnew = in.s;
         }
-        if (HSS != 0 && own && rb >= y0 && rb < y1) rho[(long long)rb * np + ln.i] = bnew;
+        if (HSS != 0 && (own & (rb >= y0) & (rb < y1))) rho[(long long)rb * np + ln.i] = bnew;
         bq[P % 3] = bnew;
         // first sweep (pointwise): row rb
         ring_push<P>(g1, clip<MODE>(ring_jf<MODE>(ln, rb, n) * bnew, ln, rb, n));
@@ -558,7 +557,7 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
             const cx<T> v =
                 cfma(ring_jf<MODE>(ln, r, n), bq[qslot<3>(P, 1)] - ring_apply<P, MODE>(L, g1, ln, r),
                      g1.v[Q::C]);
-            if (own && r >= y0 && r < y1) x[(long long)r * np + ln.i] = v;
+            if (own & (r >= y0) & (r < y1)) x[(long long)r * np + ln.i] = v;
             ring_push<P>(g2, clip<MODE>(v, ln, r, n));
         }
         // residual: row rb - 2
@@ -569,17 +568,18 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         // restriction at the fine row rb - 3 when even
         {
             const int rr = rb - 3;
-            if (!(rr & 1) && rr >= y0 && rr < y1) {
+            if (!(rr & 1) & (rr >= y0) & (rr < y1)) {
                 const cx<T> v = ring_restrict<P>(gr3);
-                if (own && !(ln.i & 1)) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
+                if (own_even) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
             }
         }
     };
 
-    constexpr int CHUNK = HSS == 1 ? 6 : 3;  // a multiple of 3 and of the R queue's 2
-    PreIn<T> buf[3];
-    load(buf[0], tb);
-    load(buf[1], tb + 1);
+    constexpr int NBUF = 3;                  // input rows in flight
+    constexpr int CHUNK = HSS == 1 ? 6 : 3;  // a multiple of 3, NBUF and the R queue's 2
+    PreIn<T> buf[NBUF];
+#pragma unroll
+    for (int k = 0; k < NBUF - 1; ++k) load(buf[k], tb + k);
     // blocks of CHUNK steps in mode MODE; the blocks whose stencil rows,
     // t - DEPTH .. t + CHUNK - 1, reach row 0 or row n run with the row mode
     // added, in loops of their own before and after the main loop
@@ -588,8 +588,8 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         auto chunk = [&](auto ec, int t) {
             auto block = [&](auto pc) {
                 constexpr int P = decltype(pc)::value;
-                load(buf[(P + 2) % 3], t + P + 2);
-                step(pc, ec, buf[P % 3], t + P);
+                load(buf[(P + NBUF - 1) % NBUF], t + P + NBUF - 1);
+                step(pc, ec, buf[P % NBUF], t + P);
             };
             block(Int<0>{});
             block(Int<1>{});
@@ -685,7 +685,7 @@ static int stream_rows(hipStream_t st, RowsKey key, int halo, bool tune, F launc
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (!tune || hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return model;
-    static const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 42, 48, 56, 64, 96, 128};
+    static const int cand[] = {2, 3, 4, 6, 8, 12, 16, 20, 24, 28, 32, 36, 40, 42, 48, 56, 64, 96, 128};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return model;
     if (hipEventCreate(&e1) != hipSuccess) {
