@@ -53,6 +53,15 @@ struct DevErr {
         }                                                                              \
     } while (0)
 
+// a streaming pass this build has no kernel for is an internal error
+#define STREAMCHK(expr)                                                                \
+    do {                                                                               \
+        if (!(expr)) {                                                                 \
+            g_last_error = std::string("unsupported streaming pass: ") + #expr;        \
+            throw DevErr{hipErrorInvalidValue};                                        \
+        }                                                                              \
+    } while (0)
+
 struct Coef {
     zd a, b, c;  // operator = a K + b M + c M_Gamma
 };
@@ -484,7 +493,7 @@ Vec<cx<T>> vcycle2d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const
         stream_pre_2d<T>(h->stream, L, L, (T)0, Vec<const cx<T>>{}, Vec<const cx<T>>{},
                          Vec<cx<T>>{}, b, x, bc, ns);
         Vec<cx<T>> ec = vcycle2d_zero<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
-        stream_sweeps_2d<T>(h->stream, L, 2, cst(x), cst(ec), b, t, Vec<cx<T>>{}, false, ns);
+        STREAMCHK(stream_sweeps_2d<T>(h->stream, L, 2, cst(x), cst(ec), b, t, Vec<cx<T>>{}, false, ns));
         return t;
     }
     pre0r_2d<T>(h->stream, L, b, x, bc, ns);
@@ -538,10 +547,10 @@ void hss_step2d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
         const bool events = prof && !stamps;
         if (events) h->prof_mark();
         if (last) {
-            if (streaming) stream_sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, Vec<cx<T>>{}, s > 0, ns);
+            if (streaming) STREAMCHK(stream_sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, Vec<cx<T>>{}, s > 0, ns));
             else sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, s > 0, ns);
         } else {
-            if (streaming) stream_sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, b1, false, ns, stamps);
+            if (streaming) STREAMCHK(stream_sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, b1, false, ns, stamps));
             else sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, false, ns);
             std::swap(x, t);
         }

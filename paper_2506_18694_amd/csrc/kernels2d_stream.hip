@@ -43,7 +43,6 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
-#include <stdexcept>
 #include <tuple>
 #include <type_traits>
 
@@ -730,7 +729,7 @@ static int stream_rows(hipStream_t st, RowsKey key, int halo, bool tune, F launc
 }
 
 template <typename T>
-void stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin,
+bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin,
                       Vec<const cx<T>> Ec, Vec<const cx<T>> B, Vec<cx<T>> Xout, Vec<cx<T>> Bc,
                       bool update, int ns, unsigned long long* ts) {
     const bool pro = Ec.base != nullptr, resid = Bc.base != nullptr;
@@ -741,7 +740,7 @@ void stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> X
     else if (S == 2 && !pro && resid && !update) kind = SK_S2R;
     else if (S == 4 && pro && !resid && !update) kind = SK_S4P;
     else if (S == 1 && !pro && !resid && !update) kind = SK_S1;
-    if (kind < 0) throw std::invalid_argument("stream_sweeps_2d: unsupported pass combination");
+    if (kind < 0) return false;
     unsigned long long* stamps = nullptr;  // set for the final launch only
     auto launch = [&](int H) {
         const StreamGrid g = stream_grid(L.n, halo, ns, H);
@@ -760,6 +759,7 @@ void stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> X
     const int H = stream_rows(st, RowsKey{kind, L.n, ns, (int)sizeof(T)}, halo, !update, launch);
     stamps = ts;
     launch(H);
+    return true;
 }
 
 template <typename T>
@@ -781,10 +781,10 @@ void stream_pre_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<c
     launch(stream_rows(st, RowsKey{SK_PRE0 + hss, L.n, ns, (int)sizeof(T)}, halo, true, launch));
 }
 
-template void stream_sweeps_2d<double>(hipStream_t, const Op2<double>&, int, Vec<const cxd>,
+template bool stream_sweeps_2d<double>(hipStream_t, const Op2<double>&, int, Vec<const cxd>,
                                        Vec<const cxd>, Vec<const cxd>, Vec<cxd>, Vec<cxd>, bool, int,
                                        unsigned long long*);
-template void stream_sweeps_2d<float>(hipStream_t, const Op2<float>&, int, Vec<const cxf>,
+template bool stream_sweeps_2d<float>(hipStream_t, const Op2<float>&, int, Vec<const cxf>,
                                       Vec<const cxf>, Vec<const cxf>, Vec<cxf>, Vec<cxf>, bool, int,
                                       unsigned long long*);
 template void stream_pre_2d<double>(hipStream_t, const Op2<double>&, const Op2<double>&, double,
