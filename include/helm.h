@@ -127,10 +127,13 @@ typedef struct {
     int    verbose;    /* > 0: print the Arnoldi residual estimate to stderr
                           every `verbose` outer iterations                   */
     int    no_stream;  /* 1: run the large 2D levels with the LDS-tiled
-                          kernels; by default they run with the register-
-                          streaming kernels (one wavefront marches up a
-                          strip of 64 columns, every sweep a pipeline stage
-                          one row behind the previous one)                   */
+                          kernels and every 3D level with one thread per
+                          node; by default the 2D levels >= 16^2 run with
+                          the register-streaming kernels (one wavefront
+                          marches up a strip of 64 columns, every sweep a
+                          pipeline stage one row behind the previous one)
+                          and the 3D levels >= 128^3 with the z-marching
+                          column-tile kernel                                 */
     int    full_reorth; /* 1: classical Gram-Schmidt twice at every Arnoldi
                           step; by default the second pass runs only for
                           the columns whose first pass kept less than

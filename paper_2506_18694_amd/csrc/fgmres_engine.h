@@ -147,7 +147,8 @@ struct Engine {
         if (h->dim == 2)
             stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), mode, 1.0, X, Bv, Y, ns);
         else
-            stencil3d<double, double>(s, make_op3<double>(b0, h->n, h->omega), mode, 1.0, X, Bv, Y, ns);
+            stencil3d<double, double>(s, make_op3<double>(b0, h->n, h->omega), mode, 1.0, X, Bv, Y, ns,
+                                      !h->opts.no_stream);
     }
     void apply_BZ(Vec<const cx<T>> Zv, Vec<cxd> Y, int ns) {
         const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
@@ -156,7 +157,7 @@ struct Engine {
                                  Vec<const cxd>{}, Y, ns);
         else
             stencil3d<double, T>(s, make_op3<double>(b0, h->n, h->omega), MODE_APPLY, 1.0, Zv,
-                                 Vec<const cxd>{}, Y, ns);
+                                 Vec<const cxd>{}, Y, ns, !h->opts.no_stream);
     }
 
     // Enqueue one step's device work.  Returns false if nothing to do.

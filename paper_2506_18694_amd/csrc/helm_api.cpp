@@ -347,7 +347,8 @@ void apply_mode(helm_t* h, int op, int l, int mode, T s, Vec<const cx<T>> X, Vec
     if (h->dim == 2) {
         stencil2d<T, T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns);
     } else {
-        stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns);
+        stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns,
+                        !h->opts.no_stream);
     }
 }
 
@@ -359,7 +360,7 @@ void resid_restrict(helm_t* h, int l, Vec<const cx<T>> X, Vec<const cx<T>> B, Ve
         resid_restrict2d<T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
     } else {
         stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), MODE_RESID, (T)1, X, B,
-                        tmp, ns);
+                        tmp, ns, !h->opts.no_stream);
         restrict3d<T>(h->stream, h->nl[l], cst(tmp), Bc, ns);
     }
 }

@@ -117,6 +117,162 @@ __global__ __launch_bounds__(BS) void k_stencil3d(Op3<T> op, T s, Vec<const cx<T
     }
 }
 
+// The same operator passes as k_stencil3d (APPLY, RESID, JACOBI) on the
+// interior nodes of a large level, marching along z through a 16 x 16
+// column tile of the mesh (one thread per (i, j), a segment of TZ output
+// planes per workgroup).  Each plane of x is read once into a
+// double-buffered LDS plane with a one-node halo (the next plane requested
+// from memory while this one is used) and reduced per column to three
+// in-plane sums: the node, its 4 edge-adjacent and its 4 diagonal
+// neighbours.  A sliding window of these sums over three planes gives the
+// 27-point apply as centre (plane l), faces (plane l's edge sum + the nodes
+// of planes l +- 1), edges (plane l's diagonal sum + the edge sums of planes
+// l +- 1) and corners (the diagonal sums of planes l +- 1).  The boundary
+// nodes are left to k_stencil3d_bnd.
+constexpr int TX = 16, TY = 16, TZ = 32;
+constexpr int TILE_MIN_N = 128;  // smallest level run with the column-tile kernel
+constexpr int PW = TX + 2, PH = TY + 2, PN = PW * PH;
+static_assert(TX * TY == BS, "one thread per column of the tile");
+static_assert(PN <= 2 * BS, "two staged values per thread cover a plane");
+
+template <typename T, typename TI, int MODE>
+__global__ __launch_bounds__(BS) void k_stencil3d_tile(Op3<T> op, T s, Vec<const cx<TI>> X,
+                                                       Vec<const cx<T>> B, Vec<cx<T>> Y,
+                                                       int tiles_x, int tiles_y, int segs) {
+    __shared__ cx<T> pl[2][PH][PW];
+    unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+    const unsigned per_slot = (unsigned)(tiles_x * tiles_y * segs);
+    const int slot = (int)(b / per_slot);
+    b %= per_slot;
+    const int seg = (int)(b % (unsigned)segs);
+    b /= (unsigned)segs;
+    const int ty = (int)(b % (unsigned)tiles_y), tx = (int)(b / (unsigned)tiles_y);
+    const int n = op.n;
+    const long long sy = n + 1, sz = sy * sy;
+    const int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+    const int i = tx * TX + li, j = ty * TY + lj;
+    // output planes [l0, l1): the interior planes of this segment
+    const int l0 = max(seg * TZ, 1), l1 = min(seg * TZ + TZ, n);
+    const cx<TI>* x = X.at(slot);
+    const cx<T>* bv = B.at(slot);
+    cx<T>* y = Y.at(slot);
+    // the two halo values this thread stages per plane (clamped into the
+    // mesh; interior nodes see only mesh nodes)
+    long long off[2];
+    int hi[2], hj[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int q = min((int)threadIdx.x + u * BS, PN - 1);
+        hi[u] = q % PW;
+        hj[u] = q / PW;
+        const int gi = min(max(tx * TX + hi[u] - 1, 0), n), gj = min(max(ty * TY + hj[u] - 1, 0), n);
+        off[u] = (long long)gj * sy + gi;
+    }
+    const bool second = (int)threadIdx.x + BS < PN;
+    const bool inner = (i > 0) & (i < n) & (j > 0) & (j < n);
+    const long long col = (long long)min(j, n) * sy + min(i, n);  // this thread's column (clamped)
+    const bool needb = MODE != MODE_APPLY;
+    const cx<T> z = mk((T)0, (T)0);
+    cx<T> v0 = z, v1 = z, bn = z;
+    auto fetch = [&](int p) {  // plane p of x, and b at (i, j, p - 1)
+        const long long base = (long long)min(max(p, 0), n) * sz;
+        v0 = cvt<T>(x[base + off[0]]);
+        if (second) v1 = cvt<T>(x[base + off[1]]);
+        if (needb) bn = bv[(long long)min(max(p - 1, 0), n) * sz + col];
+    };
+    fetch(l0 - 1);
+    pl[0][hj[0]][hi[0]] = v0;
+    if (second) pl[0][hj[1]][hi[1]] = v1;
+    fetch(l0);
+    cx<T> a0m = z, a1m = z, a2m = z, a0c = z, a1c = z, a2c = z;  // sums of planes p-2, p-1
+    cx<T> bc = z;                                                 // b at the output node
+    int k = 0;
+    for (int p = l0 - 1; p <= l1; ++p) {
+        __syncthreads();
+        // stage plane p + 1 (requested one step ago) into the other buffer
+        // after this step's reads of it have been fenced by the barrier
+        const cx<T> s0 = v0, s1 = v1, bnext = bn;
+        if (p + 2 <= l1) fetch(p + 2);
+        const cx<T>(*pc)[PW] = pl[k];
+        const cx<T> a0 = pc[lj + 1][li + 1];
+        const cx<T> a1 = (pc[lj + 1][li] + pc[lj + 1][li + 2]) + (pc[lj][li + 1] + pc[lj + 2][li + 1]);
+        const cx<T> a2 = (pc[lj][li] + pc[lj][li + 2]) + (pc[lj + 2][li] + pc[lj + 2][li + 2]);
+        const int l = p - 1;  // output plane: window p-2, p-1, p
+        if (inner && l >= l0 && l < l1) {
+            const long long t = (long long)l * sz + col;
+            const cx<T> f = a1c + (a0m + a0);
+            const cx<T> e = a2c + (a1m + a1);
+            const cx<T> c3 = a2m + a2;
+            const cx<T> lx = cfma(op.wInt[3], c3, cfma(op.wInt[2], e, cfma(op.wInt[1], f, op.wInt[0] * a0c)));
+            if (MODE == MODE_APPLY) y[t] = lx;
+            else if (MODE == MODE_RESID) y[t] = s * (bc - lx);
+            else y[t] = cfma(op.odC, bc - lx, a0c);
+        }
+        a0m = a0c;
+        a1m = a1c;
+        a2m = a2c;
+        a0c = a0;
+        a1c = a1;
+        a2c = a2;
+        bc = bnext;
+        if (p + 1 <= l1) {
+            pl[k ^ 1][hj[0]][hi[0]] = s0;
+            if (second) pl[k ^ 1][hj[1]][hi[1]] = s1;
+        }
+        k ^= 1;
+    }
+}
+
+// The boundary nodes of a level (the planes l = 0 and l = n, then the ring
+// i in {0, n} or j in {0, n} of every other plane), one thread each, with
+// the general tensor-product row.
+template <typename T, typename TI, int MODE>
+__global__ __launch_bounds__(BS) void k_stencil3d_bnd(Op3<T> op, T s, Vec<const cx<TI>> X,
+                                                      Vec<const cx<T>> B, Vec<cx<T>> Y,
+                                                      long long NB, unsigned gx) {
+    const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int slot = lin / gx;
+    const long long q = (long long)(lin % gx) * BS + threadIdx.x;
+    if (q >= NB) return;
+    const int n = op.n, W = n + 1;
+    const long long sy = W, sz = sy * sy, plane = (long long)W * W, ring = 4LL * W - 4;
+    int i, j, l;
+    if (q < 2 * plane) {
+        l = q < plane ? 0 : n;
+        const long long r = q < plane ? q : q - plane;
+        j = (int)(r / W);
+        i = (int)(r - (long long)j * W);
+    } else {
+        const long long r = q - 2 * plane;
+        l = 1 + (int)(r / ring);
+        const int e = (int)(r - (long long)(l - 1) * ring);
+        if (e < W) {
+            j = 0;
+            i = e;
+        } else if (e < 2 * W) {
+            j = n;
+            i = e - W;
+        } else if (e < 3 * W - 2) {
+            i = 0;
+            j = e - 2 * W + 1;
+        } else {
+            i = n;
+            j = e - (3 * W - 2) + 1;
+        }
+    }
+    const long long t = (long long)l * sz + (long long)j * sy + i;
+    cx<T> d;
+    const cx<T> lx = apply3_general<T, TI>(op, X.at(slot), i, j, l, t, sy, sz, &d);
+    cx<T>* y = Y.at(slot);
+    if (MODE == MODE_APPLY) {
+        y[t] = lx;
+    } else if (MODE == MODE_RESID) {
+        y[t] = s * (B.at(slot)[t] - lx);
+    } else {
+        y[t] = cfma(cdiv(mk(op.omega, (T)0), d), B.at(slot)[t] - lx, ld3<T>(X.at(slot), t));
+    }
+}
+
 // b_c = P^T r for trilinear P: weights 1 (even offset) or 1/2 (odd) per axis.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict3d(int n, Vec<const cx<T>> R, Vec<cx<T>> Bc,
@@ -184,24 +340,34 @@ inline unsigned blocks(long long N) { return (unsigned)((N + BS - 1) / BS); }
 
 template <typename T, typename TI>
 void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>> X,
-               Vec<const cx<T>> B, Vec<cx<T>> Y, int nslots) {
+               Vec<const cx<T>> B, Vec<cx<T>> Y, int nslots, bool tiled_ok) {
     const long long N = (long long)(op.n + 1) * (op.n + 1) * (op.n + 1);
     const unsigned gx = blocks(N);
-    dim3 grid(gx * nslots);
+    const int tiles = (op.n + 1 + TX - 1) / TX, segs = (op.n + 1 + TZ - 1) / TZ;
+    const dim3 tgrid((unsigned)(tiles * tiles * segs * nslots));
+    const long long W = op.n + 1, NB = 2 * W * W + (W - 2) * (4 * W - 4);
+    const unsigned gb = blocks(NB);
+    // the column-tile kernel on levels large enough to fill the chip with
+    // tiles; below that, one thread per node
+    const bool tiled = tiled_ok && op.n >= TILE_MIN_N;
+#define HELM_S3(M)                                                                                  \
+    do {                                                                                            \
+        if (tiled) {                                                                                \
+            k_stencil3d_tile<T, TI, M><<<tgrid, BS, 0, st>>>(op, s, X, B, Y, tiles, tiles, segs);   \
+            k_stencil3d_bnd<T, TI, M><<<gb * nslots, BS, 0, st>>>(op, s, X, B, Y, NB, gb);          \
+        } else {                                                                                    \
+            k_stencil3d<T, TI, M><<<dim3(gx * nslots), BS, 0, st>>>(op, s, X, B, Y, N, gx);         \
+        }                                                                                           \
+    } while (0)
     switch (mode) {
-        case MODE_APPLY:
-            k_stencil3d<T, TI, MODE_APPLY><<<grid, BS, 0, st>>>(op, s, X, B, Y, N, gx);
-            break;
-        case MODE_RESID:
-            k_stencil3d<T, TI, MODE_RESID><<<grid, BS, 0, st>>>(op, s, X, B, Y, N, gx);
-            break;
-        case MODE_JACOBI:
-            k_stencil3d<T, TI, MODE_JACOBI><<<grid, BS, 0, st>>>(op, s, X, B, Y, N, gx);
-            break;
+        case MODE_APPLY: HELM_S3(MODE_APPLY); break;
+        case MODE_RESID: HELM_S3(MODE_RESID); break;
+        case MODE_JACOBI: HELM_S3(MODE_JACOBI); break;
         case MODE_JACOBI0:
-            k_stencil3d<T, TI, MODE_JACOBI0><<<grid, BS, 0, st>>>(op, s, X, B, Y, N, gx);
+            k_stencil3d<T, TI, MODE_JACOBI0><<<dim3(gx * nslots), BS, 0, st>>>(op, s, X, B, Y, N, gx);
             break;
     }
+#undef HELM_S3
 }
 
 template <typename T>
@@ -219,11 +385,11 @@ void prolong3d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslo
 }
 
 template void stencil3d<double, double>(hipStream_t, const Op3<double>&, int, double,
-                                        Vec<const cxd>, Vec<const cxd>, Vec<cxd>, int);
+                                        Vec<const cxd>, Vec<const cxd>, Vec<cxd>, int, bool);
 template void stencil3d<double, float>(hipStream_t, const Op3<double>&, int, double,
-                                       Vec<const cxf>, Vec<const cxd>, Vec<cxd>, int);
+                                       Vec<const cxf>, Vec<const cxd>, Vec<cxd>, int, bool);
 template void stencil3d<float, float>(hipStream_t, const Op3<float>&, int, float, Vec<const cxf>,
-                                      Vec<const cxf>, Vec<cxf>, int);
+                                      Vec<const cxf>, Vec<cxf>, int, bool);
 template void restrict3d<double>(hipStream_t, int, Vec<const cxd>, Vec<cxd>, int);
 template void restrict3d<float>(hipStream_t, int, Vec<const cxf>, Vec<cxf>, int);
 template void prolong3d<double>(hipStream_t, int, Vec<const cxd>, Vec<cxd>, int);

@@ -98,9 +98,12 @@ void vcycle_small(hipStream_t st, const SmallCycle<T>& sc, size_t lds_bytes, con
                   int nc, Vec<const cx<T>> B, Vec<cx<T>> X, int ns);
 
 // ---- 3D Q1 stencils (kernels3d.hip) ---------------------------------------
+// tiled: levels n >= 128 run the z-marching column-tile kernel for the
+// interior nodes and a boundary-node kernel; otherwise (and for
+// MODE_JACOBI0) one thread per node
 template <typename T, typename TI>
 void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>> X,
-               Vec<const cx<T>> B, Vec<cx<T>> Y, int nslots);
+               Vec<const cx<T>> B, Vec<cx<T>> Y, int nslots, bool tiled = true);
 template <typename T>
 void restrict3d(hipStream_t st, int n, Vec<const cx<T>> R, Vec<cx<T>> Bc, int nslots);
 template <typename T>

@@ -35,7 +35,7 @@ def _inputs(N, nrhs, seed, prec):
 
 
 CASES_2D = [(2, 1), (5, 1), (24, 3), (33, 1), (64, 3)]
-CASES_3D = [(2, 1), (4, 2), (7, 1), (16, 2)]
+CASES_3D = [(2, 1), (4, 2), (7, 1), (16, 2), (32, 3)]  # 32: ragged tiles, two z segments
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -54,7 +54,7 @@ def test_operator_apply(op, dim, n, levels, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("dim,n,levels", [(2, 64, 3), (2, 24, 3), (3, 8, 3), (3, 16, 2)])
+@pytest.mark.parametrize("dim,n,levels", [(2, 64, 3), (2, 24, 3), (3, 8, 3), (3, 16, 2), (3, 32, 3)])
 def test_transfer_and_smoother_steps(dim, n, levels, prec):
     k, dh = 6.0, 6.0
     dt = "complex128" if prec == "fp64" else "complex64"
@@ -85,6 +85,32 @@ def test_transfer_and_smoother_steps(dim, n, levels, prec):
         s.prolong_correct(to_dev(e, dt), xd, level=l)
         refp = np.stack([xi + lev.P @ ei for xi, ei in zip(x, e)])
         assert rel_err(to_host(xd), refp) < TOL[prec], ("prolong", l)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_3d_column_tile_kernel_matches_one_thread_per_node(prec, tol):
+    """At 128^3 the operator passes run the z-marching column-tile kernel
+    (interior) plus the boundary-node kernel; the one-thread-per-node kernel
+    (pinned to the oracle at the smaller sizes above) computes the same
+    values up to summation order: every mode, two columns, the last tile
+    and z segment ragged (129 nodes per side)."""
+    n, levels, k = 128, 5, 9.0
+    dt = "complex128" if prec == "fp64" else "complex64"
+    tiled = _solver(3, n, levels, k, k, prec)
+    plain = _solver(3, n, levels, k, k, prec, streaming=False)
+    N = tiled.nodes(0)
+    x = to_dev(_inputs(N, 2, 71, prec), dt)
+    b = to_dev(_inputs(N, 2, 72, prec), dt)
+    for op in ("L", "B0"):
+        ya = to_host(tiled.apply(op, x))
+        yb = to_host(plain.apply(op, x))
+        assert rel_err(ya, yb) < tol, op
+    assert rel_err(to_host(tiled.jacobi(b, x)), to_host(plain.jacobi(b, x))) < tol
+    assert rel_err(to_host(tiled.restrict_residual(x, b)), to_host(plain.restrict_residual(x, b))) < tol
+    R = to_dev(_inputs(N, 2, 73, prec), dt)
+    assert rel_err(to_host(tiled.hss_residual(R, x)), to_host(plain.hss_residual(R, x))) < tol
+    tiled.close()
+    plain.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -120,7 +146,8 @@ def test_hss_residual(prec):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-4)])
-@pytest.mark.parametrize("dim,n,levels,k", [(2, 64, 3, 10.0), (2, 96, 4, 15.0), (3, 16, 3, 4.0)])
+@pytest.mark.parametrize("dim,n,levels,k", [(2, 64, 3, 10.0), (2, 96, 4, 15.0), (3, 16, 3, 4.0),
+                                             (3, 32, 3, 6.0)])
 def test_vcycle_matches_oracle(dim, n, levels, k, prec, tol):
     dt = "complex128" if prec == "fp64" else "complex64"
     s = _solver(dim, n, levels, k, k, prec, restart=4)
