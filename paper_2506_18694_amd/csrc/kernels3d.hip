@@ -49,26 +49,36 @@ __device__ __forceinline__ cx<T> apply3_interior(const Op3<T>& op, const cx<TI>*
     return cfma(op.wInt[3], k, cfma(op.wInt[2], e, cfma(op.wInt[1], f, op.wInt[0] * c)));
 }
 
+// Every neighbour is loaded first (an absent one at the centre's address),
+// so that the 27 loads are in flight together; the 1D factors of an absent
+// neighbour are zero, so its weight vanishes.
 template <typename T, typename TI>
 __device__ __forceinline__ cx<T> apply3_general(const Op3<T>& op, const cx<TI>* x, int i, int j,
                                                 int l, long long t, long long sy, long long sz,
                                                 cx<T>* diag) {
     const int n = op.n;
+    cx<T> v[27];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const bool in = (l + dz >= 0) & (l + dz <= n) & (j + dy >= 0) & (j + dy <= n) &
+                                (i + dx >= 0) & (i + dx <= n);
+                v[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1] = ld3<T>(x, in ? t + dz * sz + dy * sy + dx : t);
+            }
     const Line3<T> fx = line_factors<T>(i, n, op.h);
     const Line3<T> fy = line_factors<T>(j, n, op.h);
     const Line3<T> fz = line_factors<T>(l, n, op.h);
     cx<T> acc = mk((T)0, (T)0);
-    for (int dz = -1; dz <= 1; ++dz) {
-        if (l + dz < 0 || l + dz > n) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            if (j + dy < 0 || j + dy > n) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (i + dx < 0 || i + dx > n) continue;
-                const cx<T> w = weight3(op, fx, fy, fz, dx, dy, dz);
-                acc = cfma(w, ld3<T>(x, t + dz * sz + dy * sy + dx), acc);
-            }
-        }
-    }
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+                acc = cfma(weight3(op, fx, fy, fz, dx, dy, dz), v[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1], acc);
     if (diag) *diag = weight3(op, fx, fy, fz, 0, 0, 0);
     return acc;
 }
@@ -118,7 +128,7 @@ __global__ __launch_bounds__(BS) void k_stencil3d(Op3<T> op, T s, Vec<const cx<T
 }
 
 // The same operator passes as k_stencil3d (APPLY, RESID, JACOBI) on the
-// interior nodes of a large level, marching along z through a 16 x 16
+// interior nodes of a large level, marching along z through a 64 x 4
 // column tile of the mesh (one thread per (i, j), a segment of TZ output
 // planes per workgroup).  Each plane of x is read once into a
 // double-buffered LDS plane with a one-node halo (the next plane requested
@@ -129,16 +139,16 @@ __global__ __launch_bounds__(BS) void k_stencil3d(Op3<T> op, T s, Vec<const cx<T
 // of planes l +- 1), edges (plane l's diagonal sum + the edge sums of planes
 // l +- 1) and corners (the diagonal sums of planes l +- 1).  The boundary
 // nodes are left to k_stencil3d_bnd.
-constexpr int TX = 16, TY = 16, TZ = 32;
+constexpr int TX = 64, TY = 4, TZ = 32;  // columns per tile (x by y) and planes per segment
 constexpr int TILE_MIN_N = 128;  // smallest level run with the column-tile kernel
-constexpr int PW = TX + 2, PH = TY + 2, PN = PW * PH;
-static_assert(TX * TY == BS, "one thread per column of the tile");
-static_assert(PN <= 2 * BS, "two staged values per thread cover a plane");
 
-template <typename T, typename TI, int MODE>
+template <typename T, typename TI, int MODE, int TX = helm::TX, int TY = helm::TY, int TZ = helm::TZ>
 __global__ __launch_bounds__(BS) void k_stencil3d_tile(Op3<T> op, T s, Vec<const cx<TI>> X,
                                                        Vec<const cx<T>> B, Vec<cx<T>> Y,
                                                        int tiles_x, int tiles_y, int segs) {
+    constexpr int PW = TX + 2, PH = TY + 2, PN = PW * PH;
+    static_assert(TX * TY == BS, "one thread per column of the tile");
+    static_assert(PN <= 2 * BS, "two staged values per thread cover a plane");
     __shared__ cx<T> pl[2][PH][PW];
     unsigned b = xcd_remap(blockIdx.x, gridDim.x);
     const unsigned per_slot = (unsigned)(tiles_x * tiles_y * segs);
@@ -343,8 +353,9 @@ void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>
                Vec<const cx<T>> B, Vec<cx<T>> Y, int nslots, bool tiled_ok) {
     const long long N = (long long)(op.n + 1) * (op.n + 1) * (op.n + 1);
     const unsigned gx = blocks(N);
-    const int tiles = (op.n + 1 + TX - 1) / TX, segs = (op.n + 1 + TZ - 1) / TZ;
-    const dim3 tgrid((unsigned)(tiles * tiles * segs * nslots));
+    const int tiles_x = (op.n + 1 + TX - 1) / TX, tiles_y = (op.n + 1 + TY - 1) / TY;
+    const int segs = (op.n + 1 + TZ - 1) / TZ;
+    const dim3 tgrid((unsigned)(tiles_x * tiles_y * segs * nslots));
     const long long W = op.n + 1, NB = 2 * W * W + (W - 2) * (4 * W - 4);
     const unsigned gb = blocks(NB);
     // the column-tile kernel on levels large enough to fill the chip with
@@ -353,7 +364,7 @@ void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>
 #define HELM_S3(M)                                                                                  \
     do {                                                                                            \
         if (tiled) {                                                                                \
-            k_stencil3d_tile<T, TI, M><<<tgrid, BS, 0, st>>>(op, s, X, B, Y, tiles, tiles, segs);   \
+            k_stencil3d_tile<T, TI, M><<<tgrid, BS, 0, st>>>(op, s, X, B, Y, tiles_x, tiles_y, segs);   \
             k_stencil3d_bnd<T, TI, M><<<gb * nslots, BS, 0, st>>>(op, s, X, B, Y, NB, gb);          \
         } else {                                                                                    \
             k_stencil3d<T, TI, M><<<dim3(gx * nslots), BS, 0, st>>>(op, s, X, B, Y, N, gx);         \
