@@ -283,65 +283,74 @@ __global__ __launch_bounds__(BS) void k_stencil3d_bnd(Op3<T> op, T s, Vec<const 
     }
 }
 
-// b_c = P^T r for trilinear P: weights 1 (even offset) or 1/2 (odd) per axis.
+// Transfers run one thread per node of a plane: blockIdx.y is the plane
+// (and slot), blockIdx.x * BS + threadIdx.x the node within the plane, so
+// no thread divides a 64-bit index.
+
+// b_c = P^T r for trilinear P: weights 1 (even offset) or 1/2 (odd) per
+// axis.  The 27 fine values are requested together (absent ones at the
+// centre's address, weight zero).
 template <typename T>
-__global__ __launch_bounds__(BS) void k_restrict3d(int n, Vec<const cx<T>> R, Vec<cx<T>> Bc,
-                                                   long long Nc, unsigned gx) {
-    const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int slot = lin / gx;
-    const long long tc = (long long)(lin % gx) * BS + threadIdx.x;
-    if (tc >= Nc) return;
-    const int nc = n / 2;
-    const long long syc = nc + 1, szc = syc * syc, sy = n + 1, sz = sy * sy;
-    const int L = (int)(tc / szc);
-    const long long rem = tc - (long long)L * szc;
-    const int J = (int)(rem / syc), I = (int)(rem - (long long)J * syc);
+__global__ __launch_bounds__(BS) void k_restrict3d(int n, Vec<const cx<T>> R, Vec<cx<T>> Bc) {
+    const int nc = n / 2, Wc = nc + 1, W = n + 1;
+    const int slot = blockIdx.y / Wc, L = blockIdx.y % Wc;
+    const int q = blockIdx.x * BS + threadIdx.x;
+    if (q >= Wc * Wc) return;
+    const int J = q / Wc, I = q - J * Wc;
+    const long long sy = W, sz = (long long)W * W;
+    const long long tc = (long long)(2 * L) * sz + (long long)(2 * J) * sy + 2 * I;
     const cx<T>* r = R.at(slot);
-    cx<T> acc = mk((T)0, (T)0);
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int l = 2 * L + dz;
-        if (l < 0 || l > n) continue;
-        const T wz = dz ? (T)0.5 : (T)1;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int j = 2 * J + dy;
-            if (j < 0 || j > n) continue;
-            const T wy = dy ? (T)0.5 : (T)1;
+    cx<T> v[27];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
-                const int i = 2 * I + dx;
-                if (i < 0 || i > n) continue;
-                const T wx = dx ? (T)0.5 : (T)1;
-                acc = acc + (wx * wy * wz) * r[(long long)l * sz + (long long)j * sy + i];
+                const bool in = (2 * L + dz >= 0) & (2 * L + dz <= n) & (2 * J + dy >= 0) &
+                                (2 * J + dy <= n) & (2 * I + dx >= 0) & (2 * I + dx <= n);
+                v[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1] = r[in ? tc + dz * sz + dy * sy + dx : tc];
             }
-        }
-    }
-    Bc.at(slot)[tc] = acc;
+    cx<T> acc = mk((T)0, (T)0);
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const bool in = (2 * L + dz >= 0) & (2 * L + dz <= n) & (2 * J + dy >= 0) &
+                                (2 * J + dy <= n) & (2 * I + dx >= 0) & (2 * I + dx <= n);
+                const T w = in ? (dx ? (T)0.5 : (T)1) * (dy ? (T)0.5 : (T)1) * (dz ? (T)0.5 : (T)1) : (T)0;
+                acc = acc + w * v[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1];
+            }
+    Bc.at(slot)[(long long)L * Wc * Wc + q] = acc;
 }
 
 // x += P e (trilinear interpolation from the n/2 mesh)
 template <typename T>
-__global__ __launch_bounds__(BS) void k_prolong3d(int n, Vec<const cx<T>> E, Vec<cx<T>> X,
-                                                  long long N, unsigned gx) {
-    const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int slot = lin / gx;
-    const long long t = (long long)(lin % gx) * BS + threadIdx.x;
-    if (t >= N) return;
-    const long long sy = n + 1, sz = sy * sy;
-    const int nc = n / 2;
-    const long long syc = nc + 1, szc = syc * syc;
-    const int l = (int)(t / sz);
-    const long long rem = t - (long long)l * sz;
-    const int j = (int)(rem / sy), i = (int)(rem - (long long)j * sy);
+__global__ __launch_bounds__(BS) void k_prolong3d(int n, Vec<const cx<T>> E, Vec<cx<T>> X) {
+    const int W = n + 1, nc = n / 2, Wc = nc + 1;
+    const int slot = blockIdx.y / W, l = blockIdx.y % W;
+    const int q = blockIdx.x * BS + threadIdx.x;
+    if (q >= W * W) return;
+    const int j = q / W, i = q - j * W;
     const int I = i >> 1, J = j >> 1, L = l >> 1;
     const int oi = i & 1, oj = j & 1, ol = l & 1;
+    const long long syc = Wc, szc = (long long)Wc * Wc;
     const cx<T>* e = E.at(slot);
-    cx<T> v = mk((T)0, (T)0);
-    for (int cz = 0; cz <= ol; ++cz)
-        for (int cy = 0; cy <= oj; ++cy)
-            for (int cx_ = 0; cx_ <= oi; ++cx_)
-                v = v + e[(long long)(L + cz) * szc + (long long)(J + cy) * syc + (I + cx_)];
-    const T w = (T)1 / (T)(1 << (oi + oj + ol));
+    // the (up to eight) coarse corners of the cell holding the node; an odd
+    // offset on an axis takes both ends of that axis with weight one half
+    const long long c0 = (long long)L * szc + (long long)J * syc + I;
+    const long long dxo = oi, dyo = oj * syc, dzo = ol * szc;
+    const cx<T> v000 = e[c0], v100 = e[c0 + dxo], v010 = e[c0 + dyo], v110 = e[c0 + dxo + dyo];
+    const cx<T> v001 = e[c0 + dzo], v101 = e[c0 + dxo + dzo], v011 = e[c0 + dyo + dzo],
+                v111 = e[c0 + dxo + dyo + dzo];
+    const cx<T> sum = ((v000 + v100) + (v010 + v110)) + ((v001 + v101) + (v011 + v111));
+    // each distinct corner appears 8 / 2^(oi+oj+ol) times in the sum, so
+    // sum / 8 is their mean (the scalings by powers of two are exact)
     cx<T>* x = X.at(slot);
-    x[t] = x[t] + w * v;
+    const long long t = (long long)l * W * W + q;
+    x[t] = x[t] + (T)0.125 * sum;
 }
 
 inline unsigned blocks(long long N) { return (unsigned)((N + BS - 1) / BS); }
@@ -383,16 +392,16 @@ void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>
 
 template <typename T>
 void restrict3d(hipStream_t st, int n, Vec<const cx<T>> R, Vec<cx<T>> Bc, int nslots) {
-    const long long Nc = (long long)(n / 2 + 1) * (n / 2 + 1) * (n / 2 + 1);
-    const unsigned gx = blocks(Nc);
-    k_restrict3d<T><<<gx * nslots, BS, 0, st>>>(n, R, Bc, Nc, gx);
+    const int Wc = n / 2 + 1;
+    const dim3 grid((unsigned)((Wc * Wc + BS - 1) / BS), (unsigned)(Wc * nslots));
+    k_restrict3d<T><<<grid, BS, 0, st>>>(n, R, Bc);
 }
 
 template <typename T>
 void prolong3d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslots) {
-    const long long N = (long long)(n + 1) * (n + 1) * (n + 1);
-    const unsigned gx = blocks(N);
-    k_prolong3d<T><<<gx * nslots, BS, 0, st>>>(n, E, X, N, gx);
+    const int W = n + 1;
+    const dim3 grid((unsigned)((W * W + BS - 1) / BS), (unsigned)(W * nslots));
+    k_prolong3d<T><<<grid, BS, 0, st>>>(n, E, X);
 }
 
 template void stencil3d<double, double>(hipStream_t, const Op3<double>&, int, double,
