@@ -102,11 +102,12 @@ typedef struct {
     int    restart;    /* FGMRES basis size; 0 = 3*ceil(k) + 30, max 2000    */
     int    max_outer;  /* outer iteration cap; 0 = 4 * restart               */
     int    x0_given;   /* 1: x holds the initial guess on entry, else x0 = 0 */
-    int    profile;    /* 1: time the finest-level smoothing launches of the
-                          solve with HIP events (2D: the four-sweep passes;
-                          3D: each Jacobi sweep; fills the sweep_* stats).
-                          A timed solve runs its preconditioner eagerly,
-                          without the captured graphs                       */
+    int    profile;    /* 1: time the finest-level smoothing launches of
+                          every tenth HSS step with HIP events (2D: the
+                          four-sweep passes; 3D: each Jacobi sweep; fills
+                          the sweep_* stats).  A timed solve runs its
+                          preconditioner eagerly, without the captured
+                          graphs                                            */
     int    mg_cycles;  /* V-cycles per inner HSS solve (each after the first
                           starts from the previous iterate).  0 = automatic:
                           with exact inner solves the HSS error contracts by
@@ -160,7 +161,7 @@ typedef struct {
     double precond_ms;           /* device time inside the preconditioner    */
     double sweep_ms;             /* profile=1: summed device time of the
                                     timed smoothing launches (see profile)    */
-    long long sweep_launches;    /* profile=1: number of those launches       */
+    long long sweep_launches;    /* profile=1: number of timed launches       */
     double sweep_bytes;          /* profile=1: algorithmic bytes they move per
                                     right-hand side: x and b read, x' written;
                                     2D adds the coarse correction read and the

@@ -219,18 +219,16 @@ struct helm_s {
     hipStream_t aux_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
-    // optional timing of the finest-level smoothing passes: the streaming
-    // four-sweep pass stamps its own start and end on the wall clock (two
-    // values per launch in d_ts, zeroed before each preconditioner
-    // application); the other passes are bracketed by HIP events
+    // optional HIP-event timing of the finest-level smoothing passes of
+    // every PROF_EVERY-th HSS step (an event record on each side of a launch
+    // costs a few microseconds of queue time, so only a sample is timed)
+    static constexpr int PROF_EVERY = 10;
     bool prof_on = false;
+    bool prof_step = true;  // the current 3D HSS step is a timed one
     std::vector<hipEvent_t> prof_ev;
     size_t prof_used = 0;
     double prof_ms = 0.0, prof_bytes = 0.0, prof_pending_bytes = 0.0;
     long long prof_launches = 0;
-    unsigned long long* d_ts = nullptr;
-    size_t ts_cap = 0, ts_used = 0;
-    double wall_khz = 0.0;  // wall-clock ticks per millisecond
 
     Coef coef(int op) const { return op_coef(op, k, delta, dh); }
 
@@ -242,11 +240,6 @@ struct helm_s {
         }
         (void)hipEventRecord(prof_ev[prof_used++], stream);
     }
-    // the next launch's pair of stamps, or null when timing is off or full
-    unsigned long long* next_stamp() {
-        if (!prof_on || !d_ts || wall_khz <= 0.0 || ts_used >= ts_cap) return nullptr;
-        return d_ts + 2 * ts_used++;
-    }
     // called after the streams have been synchronised
     void prof_collect() {
         for (size_t q = 0; q + 1 < prof_used; q += 2) {
@@ -254,19 +247,6 @@ struct helm_s {
             if (hipEventElapsedTime(&ms, prof_ev[q], prof_ev[q + 1]) != hipSuccess) continue;
             prof_ms += ms;
             ++prof_launches;
-        }
-        if (ts_used) {
-            std::vector<unsigned long long> v(2 * ts_used);
-            if (hipMemcpyAsync(v.data(), d_ts, sizeof(unsigned long long) * v.size(),
-                               hipMemcpyDeviceToHost, stream) == hipSuccess &&
-                hipStreamSynchronize(stream) == hipSuccess) {
-                for (size_t q = 0; q < ts_used; ++q)
-                    if (v[2 * q + 1] > v[2 * q]) {
-                        prof_ms += (double)(v[2 * q + 1] - v[2 * q]) / wall_khz;
-                        ++prof_launches;
-                    }
-            }
-            ts_used = 0;
         }
         prof_bytes += prof_pending_bytes;
         prof_pending_bytes = 0.0;
@@ -382,7 +362,7 @@ void vcycle(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cx<T>> b, Ve
         return;
     }
     const T one = (T)1;
-    const bool prof = h->prof_on && l == 0;
+    const bool prof = h->prof_on && h->prof_step && l == 0;
     auto sweep = [&](Vec<const cx<T>> xin, Vec<cx<T>> xout) {
         if (prof) h->prof_mark();
         apply_mode<T>(h, HELM_OP_L, l, MODE_JACOBI, one, xin, b, xout, ns);
@@ -542,21 +522,18 @@ void hss_step2d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
         const bool last = q == h->cycles - 1;
         // the profiled kernel is the four-sweep pass (the single two-sweep
         // update pass when only one cycle is used)
-        const bool prof = h->prof_on && (h->cycles == 1 || !last);
-        // the streaming four-sweep pass times itself; other passes use events
-        unsigned long long* stamps = prof && streaming && !last ? h->next_stamp() : nullptr;
-        const bool events = prof && !stamps;
-        if (events) h->prof_mark();
+        const bool prof = h->prof_on && (h->cycles == 1 || !last) && s % helm_s::PROF_EVERY == 0;
+        if (prof) h->prof_mark();
         if (last) {
             if (streaming) STREAMCHK(stream_sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, Vec<cx<T>>{}, s > 0, ns));
             else sweeps_2d<T>(h->stream, L, 2, cst(x), ec, cst(rho), u, s > 0, ns);
         } else {
-            if (streaming) STREAMCHK(stream_sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, b1, false, ns, stamps));
+            if (streaming) STREAMCHK(stream_sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, b1, false, ns));
             else sweeps_2d<T>(h->stream, L, 4, cst(x), ec, cst(rho), t, false, ns);
             std::swap(x, t);
         }
         if (prof) {
-            if (events) h->prof_mark();
+            h->prof_mark();
             // algorithmic bytes: x, b and e_c (a quarter vector) read, x'
             // written, and with the streaming pass b_c (a quarter vector)
             // written; the update pass reads and writes u instead
@@ -578,8 +555,10 @@ void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const T c = (T)(2.0 * h->k / (h->k + 1.0));
     if (s == 0) zero<T>(h->stream, u.base, N * ns);
     apply_mode<T>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c, cst(u), cst(R), rho, ns);
+    h->prof_step = s % helm_s::PROF_EVERY == 0;
     vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns);
     for (int q = 1; q < h->cycles; ++q) vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
+    h->prof_step = true;
     axpy1<T>(h->stream, N, (T)1, cst(e), u, ns);
 }
 
@@ -686,7 +665,6 @@ void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
 template <typename T>
 void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<cx<T>> z, int ns) {
     const long long N = h->Nl[0];
-    if (h->prof_on && h->d_ts) zero<double>(h->stream, reinterpret_cast<cxd*>(h->d_ts), (long long)h->ts_cap);
     copy_cast<T, double>(h->stream, N, v, at_ws<cx<T>>(ws, Lw.R, N), ns);
     // optionally two slot groups on two streams when there are several columns
     const int ng = (ns >= 2 && h->opts.split) ? 2 : 1;
@@ -787,18 +765,6 @@ int solve_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void*
     E.init(h, ws, nrhs, tol);
     ensure_cycles<T>(h, E.Lw, ws);
     h->prof_on = h->opts.profile != 0;
-    if (h->prof_on) {
-        // room for every timed launch of one preconditioner application
-        const size_t need = (size_t)h->hss_steps * (size_t)(h->cycles + 1) * 2;
-        if (h->ts_cap < need) {
-            if (h->d_ts) HIPCHK(hipFree(h->d_ts));
-            h->d_ts = nullptr;
-            h->ts_cap = 0;
-            HIPCHK(hipMalloc(reinterpret_cast<void**>(&h->d_ts), 2 * sizeof(unsigned long long) * need));
-            h->ts_cap = need;
-        }
-    }
-    h->ts_used = 0;
     h->prof_used = 0;
     h->prof_ms = h->prof_bytes = h->prof_pending_bytes = 0.0;
     h->prof_launches = 0;
@@ -957,11 +923,6 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
         h->omega = o.omega;
         h->stream = static_cast<hipStream_t>(hip_stream);
         HIPCHK(hipGetDevice(&h->device));
-        {
-            int khz = 0;
-            if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess)
-                h->wall_khz = khz;
-        }
         h->hss_steps = o.hss_steps > 0 ? o.hss_steps : (int)(o.hss_m * std::ceil(k));
         h->cycles = o.mg_cycles > 0 ? o.mg_cycles : 2;
         h->cycles_auto = o.mg_cycles == 0;
@@ -1054,9 +1015,6 @@ int helm_destroy(helm_t* h) {
     h->d_cinv = nullptr;
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
-    if (h->d_ts) (void)hipFree(h->d_ts);
-    h->d_ts = nullptr;
-    h->ts_cap = 0;
     release_handle_objects(h);
     delete h;
     return rc;

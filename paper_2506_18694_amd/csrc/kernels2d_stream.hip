@@ -349,22 +349,10 @@ struct SweepIn {
     cx<T> x, b, e0, e1, u;
 };
 
-// Launch timing without host events: with ts set, the first workgroup's
-// first thread stores the start (ts[0]) and every wavefront that ran a unit
-// raises ts[1] to its end, both on the constant-rate wall clock; the host
-// zeroes ts before the launch.
-__device__ __forceinline__ void stamp_start(unsigned long long* ts) {
-    if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = (unsigned long long)wall_clock64();
-}
-__device__ __forceinline__ void stamp_end(unsigned long long* ts) {
-    if (ts && (threadIdx.x % WAVE) == 0) atomicMax(ts + 1, (unsigned long long)wall_clock64());
-}
-
 template <typename T, int S, bool PROLONG, bool RESID, bool UPDATE>
 __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) void k_stream_sweeps(
     Op2<T> L, Vec<const cx<T>> Xin, Vec<const cx<T>> Ec, Vec<const cx<T>> Bv, Vec<cx<T>> Xout,
-    Vec<cx<T>> Bc, StreamGrid gr, unsigned long long* ts) {
-    stamp_start(ts);
+    Vec<cx<T>> Bc, StreamGrid gr) {
     constexpr int DEPTH = S + (RESID ? 2 : 0);  // lag of the deepest stage
     constexpr int HALO = DEPTH;
     constexpr int NR = S + (RESID ? 2 : 0);
@@ -487,7 +475,6 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
     } else {
         march(Int<0>{});
     }
-    stamp_end(ts);
 }
 
 // ---- k_stream_pre -----------------------------------------------------------
@@ -731,7 +718,7 @@ static int stream_rows(hipStream_t st, RowsKey key, int halo, bool tune, F launc
 template <typename T>
 bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin,
                       Vec<const cx<T>> Ec, Vec<const cx<T>> B, Vec<cx<T>> Xout, Vec<cx<T>> Bc,
-                      bool update, int ns, unsigned long long* ts) {
+                      bool update, int ns) {
     const bool pro = Ec.base != nullptr, resid = Bc.base != nullptr;
     const int halo = S + (resid ? 2 : 0);
     int kind = -1;
@@ -741,12 +728,11 @@ bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> X
     else if (S == 4 && pro && !resid && !update) kind = SK_S4P;
     else if (S == 1 && !pro && !resid && !update) kind = SK_S1;
     if (kind < 0) return false;
-    unsigned long long* stamps = nullptr;  // set for the final launch only
     auto launch = [&](int H) {
         const StreamGrid g = stream_grid(L.n, halo, ns, H);
         const unsigned nb = stream_blocks(g);
 #define HELM_STREAM(SS, PP, RR, UU) \
-    k_stream_sweeps<T, SS, PP, RR, UU><<<nb, WAVE * SW, 0, st>>>(L, Xin, Ec, B, Xout, Bc, g, stamps)
+    k_stream_sweeps<T, SS, PP, RR, UU><<<nb, WAVE * SW, 0, st>>>(L, Xin, Ec, B, Xout, Bc, g)
         if (kind == SK_S4R) HELM_STREAM(4, true, true, false);
         else if (kind == SK_S2P && update) HELM_STREAM(2, true, false, true);
         else if (kind == SK_S2P) HELM_STREAM(2, true, false, false);
@@ -756,9 +742,7 @@ bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> X
 #undef HELM_STREAM
     };
     // u += x is not safe to repeat: the update launch only looks up
-    const int H = stream_rows(st, RowsKey{kind, L.n, ns, (int)sizeof(T)}, halo, !update, launch);
-    stamps = ts;
-    launch(H);
+    launch(stream_rows(st, RowsKey{kind, L.n, ns, (int)sizeof(T)}, halo, !update, launch));
     return true;
 }
 
@@ -782,11 +766,9 @@ void stream_pre_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<c
 }
 
 template bool stream_sweeps_2d<double>(hipStream_t, const Op2<double>&, int, Vec<const cxd>,
-                                       Vec<const cxd>, Vec<const cxd>, Vec<cxd>, Vec<cxd>, bool, int,
-                                       unsigned long long*);
+                                       Vec<const cxd>, Vec<const cxd>, Vec<cxd>, Vec<cxd>, bool, int);
 template bool stream_sweeps_2d<float>(hipStream_t, const Op2<float>&, int, Vec<const cxf>,
-                                      Vec<const cxf>, Vec<const cxf>, Vec<cxf>, Vec<cxf>, bool, int,
-                                      unsigned long long*);
+                                      Vec<const cxf>, Vec<const cxf>, Vec<cxf>, Vec<cxf>, bool, int);
 template void stream_pre_2d<double>(hipStream_t, const Op2<double>&, const Op2<double>&, double,
                                     Vec<const cxd>, Vec<const cxd>, Vec<cxd>, Vec<const cxd>,
                                     Vec<cxd>, Vec<cxd>, int);

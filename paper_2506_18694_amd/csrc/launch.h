@@ -62,13 +62,11 @@ StreamGrid stream_grid(int n, int halo, int ns, int H);
 // update, x_out += result; when Bc.base is set, also b_c = P^T (b - L x_out)
 // on the n/2 mesh.  Supported: (S, prolong, restrict, update) in
 // {(4,1,1,0), (2,1,0,1), (2,1,0,0), (2,0,1,0), (4,1,0,0), (1,0,0,0)};
-// returns false (and launches nothing) for any other.  ts (device, nullable,
-// two zeroed values): the launch's start and end on the wall clock
-// (wall_clock64, hipDeviceAttributeWallClockRate).
+// returns false (and launches nothing) for any other.
 template <typename T>
 bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin,
                       Vec<const cx<T>> Ec, Vec<const cx<T>> B, Vec<cx<T>> Xout, Vec<cx<T>> Bc,
-                      bool update, int ns, unsigned long long* ts = nullptr);
+                      bool update, int ns);
 // two zero-guess pre-smoothing sweeps x for L x = b and b_c = P^T (b - L x);
 // b given (B.base set), or b = rho = c (R - B_shift u) (U.base set) or
 // rho = c R (neither), rho then written.

@@ -95,9 +95,9 @@ def test_3d_small_solve():
 
 
 def test_profiled_solve_times_graph_launches():
-    """Timing the finest-level four-sweep passes (event nodes inside the
-    captured graphs, or event records between eager launches) changes no
-    result; every timed launch moves 3.5 vectors per right-hand side."""
+    """Timing the finest-level four-sweep passes of every tenth HSS step
+    with HIP events (the timed solve runs eagerly) changes no result; every
+    timed launch moves 3.5 vectors per right-hand side."""
     n, k, levels = 64, 10.0, 3
     pr = osolver.Problem(2, n, k, k, levels=levels)
     b = (pr.M @ W.gaussian_nodal(2, n, (0.5, 0.5), 0.05))[None]
@@ -111,8 +111,9 @@ def test_profiled_solve_times_graph_launches():
         assert np.array_equal(out[True][0], out[False][0])
         assert out[False][1]["sweep_launches"] == 0
         st = out[True][1]
-        # two timed four-sweep passes per HSS step (three cycles)
-        assert st["sweep_launches"] >= 2 * st["hss_steps"] * st["outer_its"]
+        # two timed four-sweep passes (three cycles) per sampled HSS step
+        sampled = (st["hss_steps"] + 9) // 10
+        assert st["sweep_launches"] >= 2 * sampled * st["outer_its"]
         assert st["sweep_ms"] > 0
         assert st["sweep_bytes"] / st["sweep_launches"] == pytest.approx(3.5 * 16 * (n + 1) ** 2,
                                                                           rel=1e-12)
