@@ -65,6 +65,12 @@ extern "C" {
                             accumulation); outer FGMRES, Arnoldi and the
                             coarsest-mesh solve stay FP64                    */
 
+/* ---- outer iterations (helm_opts.outer) ---------------------------------- */
+#define HELM_OUTER_FGMRES      0  /* flexible right-preconditioned GMRES (Sec. 5.1) */
+#define HELM_OUTER_RICHARDSON  1  /* preconditioned Richardson, the stationary
+                                     iteration of Sec. 4:
+                                     x <- x + B~^{-1} (rhs - B x)              */
+
 /* ---- operators for helm_apply (all a K + b M + c M_Gamma) --------------- */
 #define HELM_OP_B0      0  /* b_0: K - k^2 M - i k M_Gamma (Sec. 2, delta = 0) */
 #define HELM_OP_BDELTA  1  /* b_delta with the handle's delta                 */
@@ -146,6 +152,11 @@ typedef struct {
                           group's finest-level passes can overlap the
                           other's latency-bound coarse levels); by default
                           all columns run as one batch on one stream        */
+    int    outer;      /* HELM_OUTER_FGMRES (default) or HELM_OUTER_RICHARDSON.
+                          Richardson computes the true residual of every
+                          column each iteration and stops a column once it
+                          meets the tolerance (restart is ignored; max_outer
+                          = 0 means 4 * (3*ceil(k) + 30))                    */
 } helm_opts;
 
 typedef struct {
@@ -172,6 +183,12 @@ typedef struct {
                                     mode; 0 when mg_cycles was given)         */
     long long reorth_passes;     /* second Gram-Schmidt passes run, summed
                                     over columns and iterations               */
+    double outer_rate;           /* average outer contraction per iteration,
+                                    (|r_J| / |r_0|)^(1/J) from the true
+                                    residuals before the first and after the
+                                    last of a column's J iterations (the
+                                    measured rate of Sec. 5.2's tables); max
+                                    over columns with J >= 1, else 0         */
 } helm_stats;
 
 /* Fill *opts with the defaults listed above. */
@@ -282,6 +299,20 @@ int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs,
  * precision mode.  v, z: complex FP64 [nrhs][N]. */
 int helm_precondition(helm_t* h, const void* v, void* z, int nrhs,
                       void* workspace);
+
+/* The preconditioner of helm_precondition with the HSS residual recorded:
+ * after HSS step s (s = 1 .. hss_steps) of column c,
+ *   res[c * (hss_steps + 1) + s] = ||v_c - B_shift u_s||_2,
+ * and res[c * (hss_steps + 1)] = ||v_c||_2, all in FP64 arithmetic on the
+ * iterate u_s in the handle's precision mode (the residual contraction of
+ * the HSS iteration that Sec. 5.2 reports as the measured rate).  The
+ * steps run eagerly (no captured graph) with one extra residual pass and
+ * one device->host copy each, so this is a diagnostic, not the fast path;
+ * z receives the same result as helm_precondition.
+ *   res: host, nrhs * (hss_steps + 1) doubles, caller-owned.
+ * Errors: HELM_EINVAL for NULL pointers or nrhs < 1; HELM_EDEVICE. */
+int helm_hss_history(helm_t* h, const void* v, void* z, int nrhs, void* workspace,
+                     double* res);
 
 /* ---- serving: continuous batching of independent solves -----------------
  * A server solves a stream of requests (one mesh, k, delta_hat and a set of

@@ -29,6 +29,7 @@ struct Column {
     int j = 0, its = 0, restarts = 0;
     bool have_bnorm = false, converged = false;
     double bnorm = 0.0, beta = 0.0, est = 1.0, true_rel = -1.0;
+    double r0 = -1.0;   // true residual norm before the first iteration
     double tol = 1e-8;  // relative residual target of this column
     std::vector<zd> H, cs, sn, g;  // Hessenberg (column-major, ld R+1), rotations, rhs
 };
@@ -283,6 +284,7 @@ struct Engine {
         for (int c : fresh_cols) {
             Column& C = col[c];
             C.beta = hn[cap + q++];
+            if (C.r0 < 0.0) C.r0 = C.beta;
             C.est = C.bnorm > 0 ? C.beta / C.bnorm : 0.0;
             if (C.bnorm == 0.0 || C.beta <= C.tol * C.bnorm || !std::isfinite(C.beta)) {
                 // already solved (or zero rhs): this step's iteration is discarded

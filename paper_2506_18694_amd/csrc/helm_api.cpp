@@ -798,7 +798,7 @@ int solve_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void*
     HIPCHK(hipStreamSynchronize(h->stream));
     h->prof_on = false;
     bool ok = true;
-    double worst = 0.0, worst_arn = 0.0;
+    double worst = 0.0, worst_arn = 0.0, rate = 0.0;
     int maxits = 0, restarts = 0;
     for (const auto& C : E.col) {
         ok = ok && C.converged;
@@ -806,6 +806,8 @@ int solve_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void*
         worst_arn = std::max(worst_arn, C.est);
         maxits = std::max(maxits, C.its);
         restarts = std::max(restarts, C.restarts);
+        if (C.its > 0 && C.r0 > 0.0)
+            rate = std::max(rate, std::pow(C.true_rel * C.bnorm / C.r0, 1.0 / C.its));
     }
     if (st) {
         st->outer_its = maxits;
@@ -823,8 +825,212 @@ int solve_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void*
         st->mg_cycles = h->cycles;
         st->vcycle_rate = h->vrate;
         st->reorth_passes = E.reorth;
+        st->outer_rate = rate;
     }
     return ok ? HELM_OK : HELM_ENOCONV;
+}
+
+// Preconditioned Richardson, the stationary iteration of Sec. 4:
+// x <- x + B~^{-1} (b - B x), per column until |b - B x| <= tol |b| or
+// max_outer iterations.  Each iteration computes the true residual of every
+// running column (one batched stencil pass and norm), reads the norms on
+// the host, and applies the preconditioner to the residuals of the columns
+// still running; a column that has converged keeps its iterate.
+template <typename T>
+int richardson_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws,
+                       helm_stats* st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const long long N = h->Nl[0];
+    const Layout Lw = layout(h, nrhs);
+    hipStream_t s = h->stream;
+    char* w = static_cast<char*>(ws);
+    int* d_cols = reinterpret_cast<int*>(w + Lw.maps);          // running column ids
+    int* d_slot = d_cols + nrhs;                                // their residual slots
+    double* d_norm = reinterpret_cast<double*>(w + Lw.dnorm);   // [0, n): |r|, [n, 2n): |b|
+    double* d_npart = reinterpret_cast<double*>(w + Lw.npart);
+    cxd* d_one = reinterpret_cast<cxd*>(w + Lw.dy);
+    cxd* r = reinterpret_cast<cxd*>(w + Lw.V);                  // residual slots
+    cx<T>* z = reinterpret_cast<cx<T>*>(w + Lw.Z);              // corrections
+    int* hmap = nullptr;
+    double* hn = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Guard {
+        int*& m;
+        double*& n;
+        hipEvent_t &a, &b;
+        ~Guard() {
+            if (m) (void)hipHostFree(m);
+            if (n) (void)hipHostFree(n);
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } guard{hmap, hn, e0, e1};
+    // pinned maps: [0, 2 nrhs) for the preconditioner pass, [2 nrhs, 3 nrhs)
+    // for the residual pass (each region is rewritten only after the copy
+    // that last read it has completed)
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hmap), sizeof(int) * 3 * nrhs, 0));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hn), sizeof(double) * 2 * nrhs, 0));
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    ensure_cycles<T>(h, Lw, ws);
+    h->prof_on = h->opts.profile != 0;
+    h->prof_used = 0;
+    h->prof_ms = h->prof_bytes = h->prof_pending_bytes = 0.0;
+    h->prof_launches = 0;
+    struct ProfOff {
+        helm_t* h;
+        ~ProfOff() { h->prof_on = false; }
+    } prof_off{h};
+    if (!h->opts.x0_given) zero<double>(s, x, N * nrhs);
+    const cxd one = mk(1.0, 0.0);
+    HIPCHK(hipMemcpyAsync(d_one, &one, sizeof(cxd), hipMemcpyHostToDevice, s));
+    norm2(s, N, Vec<const cxd>{rhs, N, 0, nullptr}, d_npart, d_norm + nrhs, 1, nrhs);
+    std::vector<double> bnorm(nrhs), rel(nrhs, 0.0), r0(nrhs, -1.0);
+    std::vector<int> its(nrhs, 0), done(nrhs, 0);
+    std::vector<int> run;
+    for (int c = 0; c < nrhs; ++c) run.push_back(c);
+    const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
+    double precond_ms = 0.0;
+    long long vcycles = 0;
+    bool first = true;
+    while (!run.empty()) {
+        const int nr = (int)run.size();
+        int* hrun = hmap + 2 * nrhs;
+        for (int q = 0; q < nr; ++q) hrun[q] = run[q];
+        HIPCHK(hipMemcpyAsync(d_cols, hrun, sizeof(int) * nr, hipMemcpyHostToDevice, s));
+        // r[q] = b[c] - B x[c] for the running columns c = run[q]
+        const Vec<const cxd> Xr{x, N, 0, d_cols}, Br{rhs, N, 0, d_cols};
+        const Vec<cxd> Rr{r, N, 0, nullptr};
+        if (h->dim == 2)
+            stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), MODE_RESID, 1.0, Xr,
+                                      Br, Rr, nr);
+        else
+            stencil3d<double, double>(s, make_op3<double>(b0, h->n, h->omega), MODE_RESID, 1.0, Xr,
+                                      Br, Rr, nr, !h->opts.no_stream);
+        norm2(s, N, cst(Rr), d_npart, d_norm, 1, nr);
+        HIPCHK(hipMemcpyAsync(hn, d_norm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (first) {
+            for (int c = 0; c < nrhs; ++c) {
+                bnorm[c] = hn[nrhs + c];
+                if (!std::isfinite(bnorm[c])) {
+                    g_last_error = "non-finite right-hand side";
+                    return HELM_EINVAL;
+                }
+            }
+            first = false;
+        }
+        if (h->prof_on) h->prof_collect();
+        float ms = 0.f;
+        if (vcycles > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) precond_ms += ms;
+        std::vector<int> next, slot;
+        for (int q = 0; q < nr; ++q) {
+            const int c = run[q];
+            const double rn = hn[q];
+            if (r0[c] < 0.0) r0[c] = rn;
+            if (bnorm[c] == 0.0) {  // zero column: x = 0
+                zero<double>(s, x + (long long)c * N, N);
+                rel[c] = 0.0;
+                done[c] = 1;
+                continue;
+            }
+            rel[c] = rn / bnorm[c];
+            if (rel[c] <= tol) done[c] = 1;
+            else if (its[c] >= h->max_outer || !std::isfinite(rn)) done[c] = 0;
+            else {
+                next.push_back(c);
+                slot.push_back(q);
+                continue;
+            }
+            run[q] = -1;
+        }
+        if (next.empty()) break;
+        // z[s] = B~^{-1} r[slot[s]], then x[next[s]] += z[s]
+        const int nn = (int)next.size();
+        for (int q = 0; q < nn; ++q) {
+            hmap[q] = next[q];
+            hmap[nrhs + q] = slot[q];
+        }
+        HIPCHK(hipMemcpyAsync(d_cols, hmap, sizeof(int) * 2 * nrhs, hipMemcpyHostToDevice, s));
+        HIPCHK(hipEventRecord(e0, s));
+        precondition<T>(h, Lw, ws, Vec<const cxd>{r, N, 0, d_slot}, Vec<cx<T>>{z, N, 0, nullptr}, nn);
+        HIPCHK(hipEventRecord(e1, s));
+        vcycles += (long long)nn * h->hss_steps * h->cycles;
+        update_solution<T>(s, N, 1, nullptr, Vec<const cx<T>>{z, N, 0, nullptr}, d_one, 0,
+                           Vec<cxd>{x, N, 0, d_cols}, nn);
+        for (int c : next) ++its[c];
+        run = next;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (h->prof_on) h->prof_collect();
+    bool ok = true;
+    double worst = 0.0, rate = 0.0;
+    int maxits = 0;
+    for (int c = 0; c < nrhs; ++c) {
+        ok = ok && done[c];
+        worst = std::max(worst, rel[c]);
+        maxits = std::max(maxits, its[c]);
+        if (its[c] > 0 && r0[c] > 0.0)
+            rate = std::max(rate, std::pow(rel[c] * bnorm[c] / r0[c], 1.0 / its[c]));
+    }
+    if (st) {
+        *st = helm_stats{};
+        st->outer_its = maxits;
+        st->restarts = 0;
+        st->hss_steps = h->hss_steps;
+        st->vcycles = vcycles;
+        st->converged = ok ? 1 : 0;
+        st->arnoldi_rel_residual = worst;
+        st->true_rel_residual = worst;
+        st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        st->precond_ms = precond_ms;
+        st->sweep_ms = h->prof_ms;
+        st->sweep_launches = h->prof_launches;
+        st->sweep_bytes = h->prof_bytes;
+        st->mg_cycles = h->cycles;
+        st->vcycle_rate = h->vrate;
+        st->reorth_passes = 0;
+        st->outer_rate = rate;
+    }
+    return ok ? HELM_OK : HELM_ENOCONV;
+}
+
+// The preconditioner with the HSS residual |v - B_shift u_s| recorded after
+// every step s (FP64 arithmetic; u_s promoted from the storage precision).
+template <typename T>
+void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>> z, int ns,
+                 double* res) {
+    const long long N = h->Nl[0];
+    hipStream_t s = h->stream;
+    const int S = h->hss_steps;
+    double* d_norm = reinterpret_cast<double*>(static_cast<char*>(ws) + Lw.dnorm);
+    double* d_npart = reinterpret_cast<double*>(static_cast<char*>(ws) + Lw.npart);
+    const Vec<cxd> rv = at_ws<cxd>(ws, Lw.V, N);
+    const Vec<const cxd> vv{v, N, 0, nullptr};
+    const Vec<const cx<T>> u = cst(at_ws<cx<T>>(ws, Lw.u, N));
+    const Coef cb = h->coef(HELM_OP_BSHIFT);
+    std::vector<double> hn(2 * (size_t)ns);
+    copy_cast<T, double>(s, N, vv, at_ws<cx<T>>(ws, Lw.R, N), ns);
+    norm2(s, N, vv, d_npart, d_norm, 1, ns);
+    HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int c = 0; c < ns; ++c) res[(size_t)c * (S + 1)] = hn[c];
+    SlotGroup g{Lw, ns, s};
+    for (int step = 0; step < S; ++step) {
+        if (h->dim == 2) hss_step2d<T>(h, g.L, ws, ns, step);
+        else hss_step3d<T>(h, g.L, ws, ns, step);
+        if (h->dim == 2)
+            stencil2d<double, T>(s, make_op2<double>(cb, h->n, h->omega), MODE_RESID, 1.0, u, vv, rv,
+                                 ns);
+        else
+            stencil3d<double, T>(s, make_op3<double>(cb, h->n, h->omega), MODE_RESID, 1.0, u, vv, rv,
+                                 ns, !h->opts.no_stream);
+        norm2(s, N, cst(rv), d_npart, d_norm, 1, ns);
+        HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < ns; ++c) res[(size_t)c * (S + 1) + step + 1] = hn[c];
+    }
+    copy_cast<T, T>(s, N, u, z, ns);
 }
 
 int status_from_exception() { return HELM_EDEVICE; }
@@ -853,6 +1059,7 @@ void helm_opts_default(helm_opts* o) {
     o->no_stream = 0;
     o->full_reorth = 0;
     o->split = 0;
+    o->outer = HELM_OUTER_FGMRES;
 }
 
 const char* helm_strerror(int status) {
@@ -901,6 +1108,7 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
     if (!(o.omega > 0.0 && o.omega < 2.0)) return HELM_EINVAL;
     if (o.precision != HELM_FP64 && o.precision != HELM_FP32_MG) return HELM_EINVAL;
     if (o.restart < 0 || o.max_outer < 0 || o.restart > 2000) return HELM_EINVAL;
+    if (o.outer != HELM_OUTER_FGMRES && o.outer != HELM_OUTER_RICHARDSON) return HELM_EINVAL;
     if (bc && bc->dirichlet_faces != 0) return HELM_ENOTSUP;
     if (o.nu1 != 2 || o.nu2 != 2) return HELM_ENOTSUP;
     const int nc_side = mesh->n >> (mesh->levels - 1);
@@ -928,6 +1136,12 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
         h->cycles_auto = o.mg_cycles == 0;
         h->restart = o.restart > 0 ? o.restart : std::min(2000, 3 * (int)std::ceil(k) + 30);
         h->max_outer = o.max_outer > 0 ? o.max_outer : 4 * h->restart;
+        // Richardson keeps one residual and one correction per column
+        if (o.outer == HELM_OUTER_RICHARDSON) {
+            h->max_outer = o.max_outer > 0 ? o.max_outer
+                                           : 4 * std::min(2000, 3 * (int)std::ceil(k) + 30);
+            h->restart = 1;
+        }
         for (int l = 0; l < h->levels; ++l) {
             const int nl = h->n >> l;
             long long Nl = 1;
@@ -1036,6 +1250,13 @@ int helm_solve(helm_t* h, const void* rhs, void* x, int nrhs, double tol, void* 
     if (!h || !rhs || !x || !workspace || nrhs < 1) return HELM_EINVAL;
     if (!(tol > 0.0 && tol < 1.0)) return HELM_EINVAL;
     try {
+        if (h->opts.outer == HELM_OUTER_RICHARDSON) {
+            if (h->prec == HELM_FP64)
+                return richardson_columns<double>(h, static_cast<const cxd*>(rhs),
+                                                  static_cast<cxd*>(x), nrhs, tol, workspace, stats);
+            return richardson_columns<float>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x),
+                                             nrhs, tol, workspace, stats);
+        }
         if (h->prec == HELM_FP64)
             return solve_columns<double>(h, static_cast<const cxd*>(rhs), static_cast<cxd*>(x),
                                          nrhs, tol, workspace, stats);
@@ -1251,6 +1472,30 @@ int helm_precondition(helm_t* h, const void* v, void* z, int nrhs, void* workspa
                                      Vec<cxd>{static_cast<cxd*>(z), N, 0, nullptr}, nrhs);
         }
         HIPCHK(hipGetLastError());
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+int helm_hss_history(helm_t* h, const void* v, void* z, int nrhs, void* workspace, double* res) {
+    if (!h || !v || !z || !workspace || !res || nrhs < 1) return HELM_EINVAL;
+    const long long N = h->Nl[0];
+    const Layout Lw = layout(h, nrhs);
+    const cxd* vp = static_cast<const cxd*>(v);
+    try {
+        if (h->prec == HELM_FP64) {
+            ensure_cycles<double>(h, Lw, workspace);
+            hss_history<double>(h, Lw, workspace, vp, Vec<cxd>{static_cast<cxd*>(z), N, 0, nullptr},
+                                nrhs, res);
+        } else {
+            ensure_cycles<float>(h, Lw, workspace);
+            hss_history<float>(h, Lw, workspace, vp, at_ws<cxf>(workspace, Lw.Z, N), nrhs, res);
+            copy_cast<double, float>(h->stream, N, cst(at_ws<cxf>(workspace, Lw.Z, N)),
+                                     Vec<cxd>{static_cast<cxd*>(z), N, 0, nullptr}, nrhs);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h->stream));
     } catch (const DevErr&) {
         return HELM_EDEVICE;
     }

@@ -8,6 +8,7 @@ that says how to build it: there is no fallback path.
 """
 
 import ctypes
+import math
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -16,13 +17,15 @@ LIB_PATH = os.path.join(_HERE, "libhelm.so")
 HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV, HELM_ENOTSUP = 0, -1, -2, -3, -4, -5
 HELM_P1_TRI_RIGHT, HELM_Q1_HEX = 1, 2
 HELM_FP64, HELM_FP32_MG = 0, 1
+HELM_OUTER_FGMRES, HELM_OUTER_RICHARDSON = 0, 1
 OPS = {"B0": 0, "BDELTA": 1, "BSHIFT": 2, "L": 3, "N": 4, "H": 5, "M": 6}
 
 # every symbol include/helm.h declares
 EXPORTS = ("helm_opts_default", "helm_strerror", "helm_create", "helm_destroy", "helm_nodes",
            "helm_workspace_bytes", "helm_solve", "helm_load_nodal", "helm_apply",
            "helm_hss_residual", "helm_jacobi", "helm_restrict_residual", "helm_prolong_correct",
-           "helm_coarse_solve", "helm_vcycle", "helm_precondition", "helm_last_error",
+           "helm_coarse_solve", "helm_vcycle", "helm_precondition", "helm_hss_history",
+           "helm_last_error",
            "helm_server_create", "helm_server_submit", "helm_server_step", "helm_server_query",
            "helm_server_load", "helm_server_destroy")
 
@@ -53,7 +56,8 @@ class helm_opts(ctypes.Structure):
                 ("profile", ctypes.c_int), ("mg_cycles", ctypes.c_int),
                 ("no_graphs", ctypes.c_int), ("no_small", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("no_stream", ctypes.c_int),
-                ("full_reorth", ctypes.c_int), ("split", ctypes.c_int)]
+                ("full_reorth", ctypes.c_int), ("split", ctypes.c_int),
+                ("outer", ctypes.c_int)]
 
 
 class helm_stats(ctypes.Structure):
@@ -64,7 +68,7 @@ class helm_stats(ctypes.Structure):
                 ("precond_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double),
                 ("sweep_launches", ctypes.c_longlong), ("sweep_bytes", ctypes.c_double),
                 ("mg_cycles", ctypes.c_int), ("vcycle_rate", ctypes.c_double),
-                ("reorth_passes", ctypes.c_longlong)]
+                ("reorth_passes", ctypes.c_longlong), ("outer_rate", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -117,6 +121,7 @@ def lib():
         "helm_coarse_solve": (I, [P, I, P, P, I]),
         "helm_vcycle": (I, [P, I, P, P, I, P]),
         "helm_precondition": (I, [P, P, P, I, P]),
+        "helm_hss_history": (I, [P, P, P, I, P, ctypes.POINTER(D)]),
         "helm_server_create": (I, [ctypes.POINTER(helm_server_opts), ctypes.POINTER(P)]),
         "helm_server_submit": (I, [P, I, I, I, D, D, P, P, I, D, ctypes.POINTER(ctypes.c_longlong)]),
         "helm_server_step": (I, [P, ctypes.POINTER(I)]),
@@ -164,7 +169,7 @@ class Solver:
                  restart=0, max_outer=0, hss_steps=0, hss_m=1, omega=2.0 / 3.0,
                  dirichlet_faces=0, profile=False, mg_cycles=0, graphs=True, small_kernel=True,
                  verbose=0, stream=None, streaming=True, split=False,
-                 full_reorth=False):
+                 full_reorth=False, outer="fgmres", x0_given=False):
         import torch
         self.torch = torch
         L = lib()
@@ -182,6 +187,11 @@ class Solver:
         opts.no_stream = 0 if streaming else 1
         opts.split = 1 if split else 0
         opts.full_reorth = 1 if full_reorth else 0
+        opts.outer = {"fgmres": HELM_OUTER_FGMRES, "richardson": HELM_OUTER_RICHARDSON}[outer]
+        opts.x0_given = 1 if x0_given else 0
+        self.x0_given = bool(x0_given)
+        # the library's step count: hss_steps, else m * ceil(k)
+        self.n_hss = int(hss_steps) if hss_steps > 0 else int(hss_m * math.ceil(float(k)))
         bc = helm_bc(dirichlet_faces)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -250,14 +260,22 @@ class Solver:
             raise ValueError("%s has %d nodes, expected %d" % (what, t.shape[-1], n_nodes))
 
     # -- the solve ------------------------------------------------------------------
-    def solve(self, rhs, x=None, tol=1e-8, workspace=None):
-        """x = B^{-1} rhs (FP64 outer FGMRES); returns (x, stats dict)."""
+    def solve(self, rhs, x=None, tol=1e-8, workspace=None, x0=None):
+        """x = B^{-1} rhs (FP64 outer FGMRES or Richardson, as built); returns
+        (x, stats dict).  x0: initial guess (copied into x; needs a solver
+        built with x0_given=True, which otherwise starts from 0)."""
         torch = self.torch
         self._check_vec(rhs, self.N, torch.complex128, "rhs")
         nrhs = self._cols(rhs)
         if x is None:
             x = torch.empty_like(rhs)
         self._check_vec(x, self.N, torch.complex128, "x")
+        if x0 is not None:
+            if not self.x0_given:
+                raise ValueError("x0 needs a Solver built with x0_given=True")
+            x.copy_(x0)
+        elif self.x0_given:
+            raise ValueError("this Solver was built with x0_given=True: pass x0")
         ws = self.workspace(nrhs) if workspace is None else workspace
         st = helm_stats()
         rc = lib().helm_solve(self.h, _ptr(rhs), _ptr(x), nrhs, float(tol), _ptr(ws),
@@ -334,6 +352,21 @@ class Solver:
         _check(lib().helm_vcycle(self.h, self.prec_code, _ptr(b), _ptr(x), nrhs,
                                  _ptr(self.workspace(nrhs))), "helm_vcycle")
         return x
+
+    def hss_history(self, v):
+        """(z, res): the preconditioner applied to v, and res[c, s] =
+        ||v_c - B_shift u_s|| after HSS step s (res[c, 0] = ||v_c||), a
+        float64 numpy array (nrhs, hss_steps + 1)."""
+        import numpy as np
+        self._check_vec(v, self.N, self.torch.complex128, "v")
+        z = self.torch.empty_like(v)
+        nrhs = self._cols(v)
+        steps = self.n_hss
+        res = np.zeros((nrhs, steps + 1), dtype=np.float64)
+        _check(lib().helm_hss_history(self.h, _ptr(v), _ptr(z), nrhs, _ptr(self.workspace(nrhs)),
+                                      res.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "helm_hss_history")
+        return z, res
 
     def precondition(self, v):
         self._check_vec(v, self.N, self.torch.complex128, "v")

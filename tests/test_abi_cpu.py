@@ -35,6 +35,7 @@ def test_strerror_and_defaults():
     o = helm.helm_opts()
     L.helm_opts_default(ctypes.byref(o))
     assert (o.precision, o.nu1, o.nu2, o.hss_m, o.x0_given) == (0, 2, 2, 1, 0)
+    assert o.outer == helm.HELM_OUTER_FGMRES
     assert abs(o.omega - 2.0 / 3.0) < 1e-15
 
 
@@ -69,6 +70,9 @@ def test_create_rejects_bad_options_and_unsupported():
     o.hss_m = 0
     assert _create(helm, L, opts=o)[0] == helm.HELM_EINVAL
     L.helm_opts_default(ctypes.byref(o))
+    o.outer = 2
+    assert _create(helm, L, opts=o)[0] == helm.HELM_EINVAL
+    L.helm_opts_default(ctypes.byref(o))
     o.nu1 = 3
     assert _create(helm, L, opts=o)[0] == helm.HELM_ENOTSUP
     assert _create(helm, L, bc=helm.helm_bc(1))[0] == helm.HELM_ENOTSUP
@@ -85,6 +89,7 @@ def test_null_handle_calls_are_rejected():
     assert L.helm_apply(None, 0, 0, 0, None, None, 1) == helm.HELM_EINVAL
     assert L.helm_vcycle(None, 0, None, None, 1, None) == helm.HELM_EINVAL
     assert L.helm_precondition(None, None, None, 1, None) == helm.HELM_EINVAL
+    assert L.helm_hss_history(None, None, None, 1, None, None) == helm.HELM_EINVAL
 
 
 def test_server_rejects_invalid_options():
