@@ -158,3 +158,37 @@ def test_fgmres_outer_rate_from_residuals(pr):
     rate = (r / np.linalg.norm(b)) ** (1.0 / st["outer_its"])    # x0 = 0: r_0 = b
     assert st["outer_rate"] == pytest.approx(rate, rel=1e-6)
     assert 0.0 < st["outer_rate"] < 1.0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 5e-4)])
+def test_paper_mesh_k32_matches_oracle(prec, tol):
+    """The paper's k = 32 mesh (184 cells, 4 levels: coarsest 23 x 23, an
+    odd size) with delta_hat = 2: the preconditioner equals the oracle's."""
+    from paper_2506_18694_amd import Solver
+    k = 32.0
+    n, levels = W.PAPER_MESHES[k]
+    pr = osolver.Problem(2, n, k, DH, levels=levels, cycles=2)
+    x0 = W.paper_initial_guess(pr.B0.shape[0], 3)
+    v = np.stack([pr.M @ W.box_source(n) - pr.B0 @ x0, W.random_complex((n + 1) ** 2, 9)])
+    s = Solver(2, n, levels, k, 0.0, DH, precision=prec, mg_cycles=2)
+    z = to_host(s.precondition(to_dev(v)))
+    ref = np.stack([pr.precond(vi, inner="mg") for vi in v])
+    assert rel_l2(z, ref) < tol
+
+
+def test_paper_k16_fgmres_rate_from_random_guess(pr):
+    """The paper's multigrid table at k = 16 (8 FGMRES iterations at
+    theta = 1, measured rate 0.2264 for both sources), with its random
+    initial guess and the tolerance relative to the initial residual (the
+    solve of B_0 e = r_0 from e = 0): the GPU path with its automatic cycle
+    count reaches the paper's rate, and both sources take the same count."""
+    from paper_2506_18694_amd import Solver
+    x0 = W.paper_initial_guess(pr.B0.shape[0], 3)
+    counts = []
+    for source in ("uniform", "box"):
+        r0 = _rhs(pr, source) - pr.B0 @ x0
+        _, st = Solver(2, NCELL, LEVELS, K, 0.0, DH).solve(to_dev(r0[None]), tol=TOL)
+        assert st["converged"] == 1
+        assert abs(st["outer_rate"] - 0.2264) < 0.01, st["outer_rate"]
+        counts.append(st["outer_its"])
+    assert counts[0] == counts[1] and 8 <= counts[0] <= 10, counts

@@ -19,7 +19,10 @@ Sommerfeld conditions on every face and V(2,2) scaled Jacobi, omega = 2/3):
   q1-256-k40       3D Q1, 256^3 hexahedra, k = 40, 6 levels, one Gaussian at a
                    seeded uniform centre (seed 0), sigma 0.03, FP32 multigrid
 The paper's own sources (uniform f = 1 and the box source on
-[0.4, 0.6]^2) are available for the paper-setting checks.
+[0.4, 0.6]^2) are available for the paper-setting checks, with the paper's
+meshes (PAPER_MESHES: c0 k^(3/2) cells per side, c0 = 1 rounded up to a
+size the multigrid hierarchy divides) and its random initial guess
+(paper_initial_guess).
 """
 
 import numpy as np
@@ -85,6 +88,20 @@ def box_source(n):
     x, y = node_coordinates(2, n)
     inside = (x >= 0.4 - 1e-12) & (x <= 0.6 + 1e-12) & (y >= 0.4 - 1e-12) & (y <= 0.6 + 1e-12)
     return inside.astype(np.float64)
+
+
+# k -> (cells per side, multigrid levels) for the paper's settings: the
+# paper takes c0 k^(3/2) cells with c0 = 1 (64, 181, 512, 1448); sizes not
+# divisible by 2^(levels-1) with a coarsest mesh of at most 4096 nodes are
+# rounded up (c0 = 1.00, 1.02, 1.00, 1.02).
+PAPER_MESHES = {16.0: (64, 3), 32.0: (184, 4), 64.0: (512, 5), 128.0: (1472, 7)}
+
+
+def paper_initial_guess(count, seed):
+    """The random initial guess of the paper's runs: real and imaginary
+    parts uniform on [0, 1), as a PETSc random vector is drawn."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.random(count) + 1j * rng.random(count)
 
 
 def random_complex(shape, seed):
