@@ -11,6 +11,22 @@ schedule here is the textbook V(nu1, nu2) cycle with zero initial guess:
 The coarse operators are rediscretised on each mesh (equal to the Galerkin
 product P^T A P for nested conforming spaces; asserted by the tests).  P is
 finite-element interpolation from `oracle.fem`.
+
+The paper's own multigrid variant (Sec. 5.3) is also here: a W-cycle whose
+smoother on every level, the coarsest included, is a few iterations of
+GMRES preconditioned by Jacobi (no coarse factorisation):
+
+    x <- GMRES_m(x; b) on level l;  b_c = P^T (b - A x);  e_c = 0;
+    e_c <- W(l + 1; b_c, e_c) twice;  x <- x + P e_c;  x <- GMRES_m(x; b),
+
+and on the coarsest level x <- GMRES_m(x; b).  GMRES_m is m iterations of
+left-preconditioned GMRES from the current x: with r = D^{-1}(b - A x) it
+returns x + V y, V an orthonormal basis of the Krylov space
+span{r, (D^{-1}A) r, ..., (D^{-1}A)^{m-1} r} and y minimising
+|D^{-1}(b - A (x + V y))|_2 (the minimal-residual property that defines
+GMRES; the basis is built by Arnoldi with modified Gram-Schmidt and the
+small least-squares problem is solved by numpy).  Left preconditioning is a
+reading: the paper names GMRES with a Jacobi preconditioner, not the side.
 """
 
 import numpy as np
@@ -42,11 +58,12 @@ class Hierarchy:
             A = combine(K, M, MG, abc)
             P = fem.prolongation(dim, nl) if l < levels - 1 else None
             self.levels.append(Level(nl, A, P))
-        coarse = self.levels[-1].A.toarray()
-        self.coarse_lu = sla.lu_factor(coarse)
+        self._coarse_lu = None
 
     def coarse_solve(self, b):
-        return sla.lu_solve(self.coarse_lu, b)
+        if self._coarse_lu is None:   # dense LU of the coarsest operator
+            self._coarse_lu = sla.lu_factor(self.levels[-1].A.toarray())
+        return sla.lu_solve(self._coarse_lu, b)
 
 
 def jacobi_sweep(level, x, b, omega):
@@ -101,3 +118,55 @@ def error_propagator(hier, l=0, nu1=2, nu2=2, omega=2.0 / 3.0):
     Bc = (np.eye(Ac.shape[0]) - Ec) @ np.linalg.inv(Ac)   # approximate coarse inverse
     C = np.eye(nl) - P @ Bc @ P.T @ A
     return np.linalg.matrix_power(S, nu2) @ C @ np.linalg.matrix_power(S, nu1)
+
+
+def gmres_jacobi(level, x, b, its):
+    """`its` iterations of Jacobi-left-preconditioned GMRES for A x = b
+    from the given x (see the module notes); returns the new x."""
+    A, D = level.A, level.D
+    r = (b - A @ x) / D
+    beta = np.linalg.norm(r)
+    if beta == 0.0:
+        return x.copy()
+    V = np.zeros((its + 1, b.size), dtype=np.complex128)
+    H = np.zeros((its + 1, its), dtype=np.complex128)
+    V[0] = r / beta
+    m = its
+    for j in range(its):                       # Arnoldi, modified Gram-Schmidt
+        w = (A @ V[j]) / D
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[i], w)
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] == 0.0:                 # the Krylov space is invariant
+            m = j + 1
+            break
+        V[j + 1] = w / H[j + 1, j]
+    g = np.zeros(m + 1, dtype=np.complex128)
+    g[0] = beta
+    y = np.linalg.lstsq(H[:m + 1, :m], g, rcond=None)[0]
+    return x + V[:m].T @ y
+
+
+def wcycle(hier, b, x, l=0, its=5):
+    """One W-cycle for A_l x = b from the given x, GMRES_its smoothing on
+    every level (the coarsest: one GMRES_its application); returns x."""
+    lev = hier.levels[l]
+    if l == len(hier.levels) - 1:
+        return gmres_jacobi(lev, x, b, its)
+    x = gmres_jacobi(lev, x, b, its)
+    bc = lev.P.T @ (b - lev.A @ x)
+    ec = np.zeros_like(bc)
+    for _ in range(2):
+        ec = wcycle(hier, bc, ec, l + 1, its)
+    x = x + lev.P @ ec
+    return gmres_jacobi(lev, x, b, its)
+
+
+def w_cycles(hier, b, count, its=5):
+    """`count` W-cycles from x = 0 (each after the first continues from the
+    previous iterate): the paper's inner HSS solve with multigrid."""
+    x = np.zeros_like(b, dtype=np.complex128)
+    for _ in range(count):
+        x = wcycle(hier, b, x, 0, its)
+    return x

@@ -18,11 +18,13 @@ from . import fem, operators as ops, hss, multigrid, krylov
 
 class Problem:
     def __init__(self, dim, n, k, delta_hat, delta=0.0, levels=1, faces=None,
-                 nu1=2, nu2=2, omega=2.0 / 3.0, m=1, cycles=2):
+                 nu1=2, nu2=2, omega=2.0 / 3.0, m=1, cycles=2, cycle="v", smooth_its=5):
         self.dim, self.n, self.k = dim, n, float(k)
         self.delta, self.delta_hat = float(delta), float(delta_hat)
         self.nu1, self.nu2, self.omega, self.m = nu1, nu2, omega, m
-        self.cycles = cycles            # V-cycles per inner HSS solve
+        self.cycles = cycles            # cycles per inner HSS solve
+        self.cycle = cycle              # "v": V(nu1, nu2) Jacobi; "w": the
+        self.smooth_its = smooth_its    # paper's W-cycle, GMRES_its smoothing
         self.K, self.M, self.MG = fem.assemble(dim, n, faces)
         K, M, MG = self.K, self.M, self.MG
         self.B0 = ops.b_delta(K, M, MG, k, delta).tocsr()
@@ -61,9 +63,12 @@ class Problem:
                                 0, self.nu1, self.nu2, self.omega)
 
     def mg_solve(self, b):
-        """Inner HSS solve by `cycles` V-cycles (x <- x + V(b - L x), x0 = 0)."""
-        return multigrid.cycles(self.hierarchy, np.asarray(b, dtype=np.complex128),
-                                self.cycles, self.nu1, self.nu2, self.omega)
+        """Inner HSS solve by `cycles` V-cycles (x <- x + V(b - L x), x0 = 0),
+        or by `cycles` of the paper's W-cycles (cycle = "w")."""
+        b = np.asarray(b, dtype=np.complex128)
+        if self.cycle == "w":
+            return multigrid.w_cycles(self.hierarchy, b, self.cycles, self.smooth_its)
+        return multigrid.cycles(self.hierarchy, b, self.cycles, self.nu1, self.nu2, self.omega)
 
     # -- preconditioner -------------------------------------------------------
     def hss_steps(self):
