@@ -71,6 +71,15 @@ extern "C" {
                                      iteration of Sec. 4:
                                      x <- x + B~^{-1} (rhs - B x)              */
 
+/* ---- multigrid cycles (helm_opts.cycle) ---------------------------------- */
+#define HELM_CYCLE_V_JACOBI   0  /* V(2,2) cycles, scaled Jacobi omega, FP64
+                                    dense solve on the coarsest mesh          */
+#define HELM_CYCLE_W_GMRES    1  /* the paper's variant (Sec. 5.3): W-cycle
+                                    whose smoother on every level, the
+                                    coarsest included, is smooth_its
+                                    iterations of Jacobi-left-preconditioned
+                                    GMRES; no coarse factorisation          */
+
 /* ---- operators for helm_apply (all a K + b M + c M_Gamma) --------------- */
 #define HELM_OP_B0      0  /* b_0: K - k^2 M - i k M_Gamma (Sec. 2, delta = 0) */
 #define HELM_OP_BDELTA  1  /* b_delta with the handle's delta                 */
@@ -157,6 +166,13 @@ typedef struct {
                           column each iteration and stops a column once it
                           meets the tolerance (restart is ignored; max_outer
                           = 0 means 4 * (3*ceil(k) + 30))                    */
+    int    cycle;      /* HELM_CYCLE_V_JACOBI (default) or HELM_CYCLE_W_GMRES.
+                          The W variant needs HELM_FP64, runs its kernels
+                          one by one (no captured graph), uses mg_cycles
+                          W-cycles per HSS step (0 = 1, the paper's choice)
+                          and places no limit on the coarsest mesh size    */
+    int    smooth_its; /* GMRES iterations per smoothing of the W variant,
+                          1..20; 0 = 5 (the paper's primal setting)         */
 } helm_opts;
 
 typedef struct {
@@ -215,9 +231,11 @@ const char* helm_last_error(void);
  * vectors live in the caller's workspace.
  * Errors: HELM_EINVAL for dim not in {2,3}, elem/dim mismatch, n < 2,
  * levels < 1, n not divisible by 2^(levels-1), k <= 0, delta < 0,
- * delta_hat <= delta, hss_m < 1, omega not in (0, 2), out == NULL, or a
+ * delta_hat <= delta, hss_m < 1, omega not in (0, 2), out == NULL, an
+ * unknown outer or cycle, smooth_its outside 0..20, or (V cycles) a
  * coarsest mesh with more than 4096 nodes; HELM_ENOTSUP for Dirichlet
- * faces or (nu1, nu2) != (2, 2); HELM_ENOMEM; HELM_EDEVICE.
+ * faces, (nu1, nu2) != (2, 2) with V cycles, or the W variant with
+ * HELM_FP32_MG; HELM_ENOMEM; HELM_EDEVICE.
  * On error *out is set to NULL and nothing is leaked.
  */
 int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
@@ -287,10 +305,12 @@ int helm_restrict_residual(helm_t* h, int level, int prec, const void* x,
 int helm_prolong_correct(helm_t* h, int level, int prec, const void* e_coarse,
                          void* x, int nrhs);
 
-/* Coarsest-mesh solve x = L_c^{-1} b in FP64 arithmetic whatever prec. */
+/* Coarsest-mesh solve x = L_c^{-1} b in FP64 arithmetic whatever prec
+ * (HELM_ENOTSUP with HELM_CYCLE_W_GMRES, which has no coarse solve). */
 int helm_coarse_solve(helm_t* h, int prec, const void* b, void* x, int nrhs);
 
-/* One V(nu1, nu2) cycle for L on level 0 with zero initial guess. */
+/* One multigrid cycle for L on level 0 with zero initial guess: V(nu1, nu2)
+ * Jacobi, or with HELM_CYCLE_W_GMRES one W-cycle of the paper's variant. */
 int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs,
                 void* workspace);
 

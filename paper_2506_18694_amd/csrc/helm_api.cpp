@@ -27,6 +27,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/helm.h"
@@ -203,6 +204,7 @@ struct helm_s {
     int prec = HELM_FP64;
     double omega = 2.0 / 3.0;
     int cycles = 2;           // V-cycles per inner HSS solve
+    int smooth_its = 5;       // GMRES iterations per smoothing (W variant)
     bool cycles_auto = true;  // choose `cycles` from the measured cycle rate
     double vrate = 0.0;       // measured V-cycle contraction (0 = not yet)
 
@@ -270,6 +272,10 @@ struct Layout {
     size_t R, u;
     size_t V, Z, Bw, Xw;
     size_t dh, dh2, dnorm, part, npart, dy, cols, maps, flag;
+    // W variant: per level the GMRES smoother's Krylov basis (m+1 vectors
+    // per slot), its Hessenberg columns (two passes), norms, coefficients
+    // and reduction partials
+    size_t gk[32], ghu, ghu2, gn, gy, gpart, gnpart;
     size_t total;
 };
 
@@ -305,6 +311,16 @@ Layout layout(const helm_t* h, int nrhs) {
     L.Z = take(smg * (size_t)nrhs * R * N);
     L.Bw = take(sizeof(cxd) * (size_t)nrhs * N);
     L.Xw = take(sizeof(cxd) * (size_t)nrhs * N);
+    if (h->opts.cycle == HELM_CYCLE_W_GMRES) {
+        const int m = h->smooth_its;
+        for (int l = 0; l < h->levels; ++l) L.gk[l] = take(sizeof(cxd) * (size_t)nrhs * (m + 1) * h->Nl[l]);
+        L.ghu = take(sizeof(cxd) * (size_t)nrhs * m * (m + 1));
+        L.ghu2 = take(sizeof(cxd) * (size_t)nrhs * (m + 1));
+        L.gn = take(sizeof(double) * (size_t)nrhs * (m + 1));
+        L.gy = take(sizeof(cxd) * (size_t)nrhs * m);
+        L.gpart = take(sizeof(cxd) * (size_t)nrhs * (m + 1) * nblk);
+        L.gnpart = take(sizeof(double) * (size_t)nrhs * nblk);
+    }
     L.total = off;
     return L;
 }
@@ -562,6 +578,117 @@ void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     axpy1<T>(h->stream, N, (T)1, cst(e), u, ns);
 }
 
+// ---- the paper's multigrid variant (Sec. 5.3): W-cycle, GMRES smoothing ----
+
+// y = D^{-1} (b - L x) (MODE_PRES; X null means x = 0) or y = D^{-1} L x
+// (MODE_PAPPLY) on level l in FP64: the Jacobi factors with omega = 1.
+void pmode(helm_t* h, int l, int mode, Vec<const cxd> X, Vec<const cxd> B, Vec<cxd> Y, int ns) {
+    const Coef cf = h->coef(HELM_OP_L);
+    if (h->dim == 2)
+        stencil2d<double, double>(h->stream, make_op2<double>(cf, h->nl[l], 1.0), mode, 1.0, X, B, Y, ns);
+    else
+        stencil3d<double, double>(h->stream, make_op3<double>(cf, h->nl[l], 1.0), mode, 1.0, X, B, Y, ns,
+                                  false);
+}
+
+// m = smooth_its iterations of Jacobi-left-preconditioned GMRES for
+// L x = b on level l, from the current x (guess) or from x = 0: the
+// Krylov basis of D^{-1} L from r = D^{-1}(b - L x) by Arnoldi with
+// classical Gram-Schmidt applied twice, the (m+1) x m least-squares
+// problem solved on the device, x += V y.  Every column works in its own
+// slot; nothing is read back to the host.
+void gmres_smooth(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cxd> b, Vec<cxd> x,
+                  bool guess, int ns) {
+    hipStream_t st = h->stream;
+    const int m = h->smooth_its;
+    const long long N = h->Nl[l];
+    char* w = static_cast<char*>(ws);
+    cxd* G = reinterpret_cast<cxd*>(w + Lw.gk[l]);
+    cxd* hu = reinterpret_cast<cxd*>(w + Lw.ghu);
+    cxd* hu2 = reinterpret_cast<cxd*>(w + Lw.ghu2);
+    double* hn = reinterpret_cast<double*>(w + Lw.gn);
+    cxd* gy = reinterpret_cast<cxd*>(w + Lw.gy);
+    cxd* part = reinterpret_cast<cxd*>(w + Lw.gpart);
+    double* npart = reinterpret_cast<double*>(w + Lw.gnpart);
+    const long long cs = (long long)(m + 1) * N;  // slot stride of the basis
+    const int hs = m * (m + 1);                    // slot stride of the Hessenberg
+    const int nblk = multidot_blocks(N);
+    auto basis = [&](int i) { return Vec<cxd>{G + (long long)i * N, cs, 0, nullptr}; };
+    const Vec<const cxd> V{G, cs, 0, nullptr};
+    if (!guess) zero<double>(st, x.base, N * ns);
+    pmode(h, l, MODE_PRES, guess ? cst(x) : Vec<const cxd>{}, b, basis(0), ns);
+    norm2(st, N, cst(basis(0)), npart, hn, m + 1, ns);
+    scale_inv(st, N, cst(basis(0)), basis(0), hn, m + 1, ns);
+    for (int j = 0; j < m; ++j) {
+        const Vec<cxd> wv = basis(j + 1);
+        cxd* hcol = hu + (long long)j * (m + 1);
+        pmode(h, l, MODE_PAPPLY, cst(basis(j)), Vec<const cxd>{}, wv, ns);
+        for (int pass = 0; pass < 2; ++pass) {
+            multidot(st, N, j + 1, nullptr, V, cst(wv), part, ns);
+            if (pass == 0) {
+                reduce_parts(st, j + 1, nullptr, nblk, part, hcol, hs, 0, ns);
+                multi_axpy(st, N, j + 1, nullptr, V, hcol, hs, wv, ns);
+            } else {
+                reduce_parts(st, j + 1, nullptr, nblk, part, hu2, m + 1, 0, ns);
+                reduce_parts(st, j + 1, nullptr, nblk, part, hcol, hs, 1, ns);
+                multi_axpy(st, N, j + 1, nullptr, V, hu2, m + 1, wv, ns);
+            }
+        }
+        norm2(st, N, cst(wv), npart, hn + j + 1, m + 1, ns);
+        scale_inv(st, N, cst(wv), wv, hn + j + 1, m + 1, ns);
+    }
+    gmres_lsq(st, m, hu, hs, hn, gy, ns);
+    update_solution<double>(st, N, m, nullptr, V, gy, m, x, ns);
+}
+
+// One W-cycle for L_l x = b from x (guess) or 0: smoothing, residual
+// restriction, two cycles on the coarse equation (the second from the
+// first's result), prolongation and correction, smoothing; the coarsest
+// level smooths once.
+void wcycle_gm(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cxd> b, Vec<cxd> x, bool guess,
+               int ns) {
+    gmres_smooth(h, Lw, ws, l, b, x, guess, ns);
+    if (l == h->levels - 1) return;
+    const long long N1 = h->Nl[l + 1];
+    Vec<cxd> bc = at_ws<cxd>(ws, Lw.mg_b[l + 1], N1);
+    Vec<cxd> xc = at_ws<cxd>(ws, Lw.mg_x[l + 1], N1);
+    resid_restrict<double>(h, l, cst(x), b, bc, at_ws<cxd>(ws, Lw.mg_t[l], h->Nl[l]), ns);
+    wcycle_gm(h, Lw, ws, l + 1, cst(bc), xc, false, ns);
+    wcycle_gm(h, Lw, ws, l + 1, cst(bc), xc, true, ns);
+    prolong<double>(h, l, cst(xc), x, ns);
+    gmres_smooth(h, Lw, ws, l, b, x, true, ns);
+}
+
+// One shifted-HSS step with the W variant: rho = c (R - B u), `cycles`
+// W-cycles (each after the first from the previous iterate), u += e.
+void hss_step_w(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
+    const long long N = h->Nl[0];
+    Vec<cxd> R = at_ws<cxd>(ws, Lw.R, N);
+    Vec<cxd> u = at_ws<cxd>(ws, Lw.u, N);
+    Vec<cxd> rho = at_ws<cxd>(ws, Lw.mg_b[0], N);
+    Vec<cxd> e = at_ws<cxd>(ws, Lw.mg_x[0], N);
+    const double c = 2.0 * h->k / (h->k + 1.0);
+    if (s == 0) zero<double>(h->stream, u.base, N * ns);
+    apply_mode<double>(h, HELM_OP_BSHIFT, 0, MODE_RESID, c, cst(u), cst(R), rho, ns);
+    for (int q = 0; q < h->cycles; ++q) wcycle_gm(h, Lw, ws, 0, cst(rho), e, q > 0, ns);
+    axpy1<double>(h->stream, N, 1.0, cst(e), u, ns);
+}
+
+inline bool w_variant(const helm_t* h) { return h->opts.cycle == HELM_CYCLE_W_GMRES; }
+
+// HSS step s of the handle's variant on the slot range described by L.
+template <typename T>
+void hss_step(helm_t* h, const Layout& L, void* ws, int ns, int s) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (w_variant(h)) {
+            hss_step_w(h, L, ws, ns, s);
+            return;
+        }
+    }
+    if (h->dim == 2) hss_step2d<T>(h, L, ws, ns, s);
+    else hss_step3d<T>(h, L, ws, ns, s);
+}
+
 // A range of slots that runs its HSS loop on a stream of its own: the
 // layout's per-slot buffers start at the range's first slot.
 struct SlotGroup {
@@ -599,8 +726,7 @@ void hss_loop(helm_t* h, void* ws, const SlotGroup* g, int ng) {
     for (int s = 0; s < h->hss_steps; ++s) {
         for (int q = 0; q < ng; ++q) {
             h->stream = g[q].st;
-            if (h->dim == 2) hss_step2d<T>(h, g[q].L, ws, g[q].ns, s);
-            else hss_step3d<T>(h, g[q].L, ws, g[q].ns, s);
+            hss_step<T>(h, g[q].L, ws, g[q].ns, s);
         }
     }
 }
@@ -667,15 +793,17 @@ void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<c
     const long long N = h->Nl[0];
     copy_cast<T, double>(h->stream, N, v, at_ws<cx<T>>(ws, Lw.R, N), ns);
     // optionally two slot groups on two streams when there are several columns
-    const int ng = (ns >= 2 && h->opts.split) ? 2 : 1;
+    // (not with the W variant, whose smoother buffers are not per group)
+    const int ng = (ns >= 2 && h->opts.split && !w_variant(h)) ? 2 : 1;
     const int n0 = ng == 2 ? (ns + 1) / 2 : ns;
     SlotGroup grp[2] = {{Lw, n0, h->stream}, {shift_slots<T>(h, Lw, n0), ns - n0, h->aux_stream}};
     if (ng == 2) {
         HIPCHK(hipEventRecord(h->ev_fork, h->stream));
         HIPCHK(hipStreamWaitEvent(h->aux_stream, h->ev_fork, 0));
     }
-    // timed runs stay eager: event timings are read between the launches
-    if (h->prof_on || h->opts.no_graphs) {
+    // timed runs stay eager: event timings are read between the launches;
+    // the W variant (thousands of small launches per step) runs eagerly too
+    if (h->prof_on || h->opts.no_graphs || w_variant(h)) {
         hss_loop<T>(h, ws, grp, ng);
     } else {
         // each group's whole HSS loop (all steps, cycles and levels) is
@@ -701,8 +829,7 @@ void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<c
                     } restore{h, h->stream};
                     h->stream = grp[q].st;
                     for (int s = 0; s < std::min(2, h->hss_steps); ++s) {
-                        if (h->dim == 2) hss_step2d<T>(h, grp[q].L, ws, grp[q].ns, s);
-                        else hss_step3d<T>(h, grp[q].L, ws, grp[q].ns, s);
+                        hss_step<T>(h, grp[q].L, ws, grp[q].ns, s);
                     }
                 }
                 hipGraph_t graph = nullptr;
@@ -740,6 +867,12 @@ void vcycle_entry(helm_t* h, const Layout& Lw, void* ws, const void* b, void* x,
     Vec<const cx<T>> bv{static_cast<const cx<T>*>(b), N, 0, nullptr};
     Vec<cx<T>> xv{static_cast<cx<T>*>(x), N, 0, nullptr};
     Vec<cx<T>> tv = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
+    if constexpr (std::is_same<T, double>::value) {
+        if (w_variant(h)) {
+            wcycle_gm(h, Lw, ws, 0, bv, xv, false, ns);
+            return;
+        }
+    }
     if (h->dim == 2) {
         Vec<cx<T>> r = vcycle2d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns);
         if (r.base != xv.base) copy_cast<T, T>(h->stream, N, cst(r), xv, ns);
@@ -1017,8 +1150,7 @@ void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>>
     for (int c = 0; c < ns; ++c) res[(size_t)c * (S + 1)] = hn[c];
     SlotGroup g{Lw, ns, s};
     for (int step = 0; step < S; ++step) {
-        if (h->dim == 2) hss_step2d<T>(h, g.L, ws, ns, step);
-        else hss_step3d<T>(h, g.L, ws, ns, step);
+        hss_step<T>(h, g.L, ws, ns, step);
         if (h->dim == 2)
             stencil2d<double, T>(s, make_op2<double>(cb, h->n, h->omega), MODE_RESID, 1.0, u, vv, rv,
                                  ns);
@@ -1060,6 +1192,8 @@ void helm_opts_default(helm_opts* o) {
     o->full_reorth = 0;
     o->split = 0;
     o->outer = HELM_OUTER_FGMRES;
+    o->cycle = HELM_CYCLE_V_JACOBI;
+    o->smooth_its = 0;
 }
 
 const char* helm_strerror(int status) {
@@ -1109,12 +1243,16 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
     if (o.precision != HELM_FP64 && o.precision != HELM_FP32_MG) return HELM_EINVAL;
     if (o.restart < 0 || o.max_outer < 0 || o.restart > 2000) return HELM_EINVAL;
     if (o.outer != HELM_OUTER_FGMRES && o.outer != HELM_OUTER_RICHARDSON) return HELM_EINVAL;
+    if (o.cycle != HELM_CYCLE_V_JACOBI && o.cycle != HELM_CYCLE_W_GMRES) return HELM_EINVAL;
+    if (o.smooth_its < 0 || o.smooth_its > 20) return HELM_EINVAL;
+    const bool wvar = o.cycle == HELM_CYCLE_W_GMRES;
     if (bc && bc->dirichlet_faces != 0) return HELM_ENOTSUP;
-    if (o.nu1 != 2 || o.nu2 != 2) return HELM_ENOTSUP;
+    if (!wvar && (o.nu1 != 2 || o.nu2 != 2)) return HELM_ENOTSUP;
+    if (wvar && o.precision != HELM_FP64) return HELM_ENOTSUP;
     const int nc_side = mesh->n >> (mesh->levels - 1);
     long long ncoarse = 1;
     for (int d = 0; d < mesh->dim; ++d) ncoarse *= (nc_side + 1);
-    if (ncoarse > 4096) return HELM_EINVAL;
+    if (!wvar && ncoarse > 4096) return HELM_EINVAL;
 
     helm_t* h = new (std::nothrow) helm_t;
     if (!h) return HELM_ENOMEM;
@@ -1132,8 +1270,9 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
         h->stream = static_cast<hipStream_t>(hip_stream);
         HIPCHK(hipGetDevice(&h->device));
         h->hss_steps = o.hss_steps > 0 ? o.hss_steps : (int)(o.hss_m * std::ceil(k));
-        h->cycles = o.mg_cycles > 0 ? o.mg_cycles : 2;
-        h->cycles_auto = o.mg_cycles == 0;
+        h->cycles = o.mg_cycles > 0 ? o.mg_cycles : (wvar ? 1 : 2);
+        h->cycles_auto = o.mg_cycles == 0 && !wvar;
+        h->smooth_its = o.smooth_its > 0 ? o.smooth_its : 5;
         h->restart = o.restart > 0 ? o.restart : std::min(2000, 3 * (int)std::ceil(k) + 30);
         h->max_outer = o.max_outer > 0 ? o.max_outer : 4 * h->restart;
         // Richardson keeps one residual and one correction per column
@@ -1149,10 +1288,12 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
             h->nl.push_back(nl);
             h->Nl.push_back(Nl);
         }
-        // coarsest-mesh dense L (from the same stencil rows the kernels use)
+        // coarsest-mesh dense L (from the same stencil rows the kernels use);
+        // the W variant smooths on the coarsest mesh instead
         const int ncs = h->nl.back();
         const int nc = (int)h->Nl.back();
         h->nc = nc;
+        if (!wvar) {
         std::vector<zd> A((size_t)nc * nc, zd(0.0));
         const Coef cf = h->coef(HELM_OP_L);
         if (h->dim == 2) {
@@ -1201,6 +1342,7 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
             return HELM_ENOMEM;
         }
         HIPCHK(hipMemcpy(h->d_cinv, Ah.data(), sizeof(cxd) * Ah.size(), hipMemcpyHostToDevice));
+        }
         // private stream used only to capture the preconditioner graph, and
         // the stream of the second slot group
         HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
@@ -1421,6 +1563,7 @@ int helm_prolong_correct(helm_t* h, int level, int prec, const void* e_coarse, v
 int helm_coarse_solve(helm_t* h, int prec, const void* b, void* x, int nrhs) {
     if (!h || !b || !x || nrhs < 1) return HELM_EINVAL;
     if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    if (!h->d_cinv) return HELM_ENOTSUP;  // the W variant has no coarse factorisation
     const long long Nc = h->Nl.back();
     try {
         if (prec == HELM_FP64)

@@ -124,6 +124,8 @@ enum StencilMode : int {
     MODE_RESID = 1,    // y = s (b - Op x)
     MODE_JACOBI = 2,   // y = x + omega D^{-1} (b - Op x)
     MODE_JACOBI0 = 3,  // y = omega D^{-1} b          (zero initial guess)
+    MODE_PRES = 4,     // y = omega D^{-1} (b - Op x)  (X null: x = 0)
+    MODE_PAPPLY = 5,   // y = omega D^{-1} Op x
 };
 
 // Remap a linear workgroup id so that each of the 8 XCDs (which receive

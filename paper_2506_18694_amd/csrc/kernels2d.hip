@@ -74,7 +74,7 @@ __global__ __launch_bounds__(BS) void k_stencil2d(Op2<T> op, T s, Vec<const cx<T
     const int i = (int)(t - (long long)j * np);
     const bool interior = (i > 0) & (i < n) & (j > 0) & (j < n);
     cx<T>* y = Y.at(slot);
-    if (MODE == MODE_JACOBI0) {
+    if (MODE == MODE_JACOBI0 || (MODE == MODE_PRES && !X.base)) {
         const cx<T>* b = B.at(slot);
         const cx<T> f = interior ? op.odC : jacobi_factor(op, i, j);
         y[t] = f * b[t];
@@ -92,6 +92,11 @@ __global__ __launch_bounds__(BS) void k_stencil2d(Op2<T> op, T s, Vec<const cx<T
     } else if (MODE == MODE_RESID) {
         const cx<T>* b = B.at(slot);
         y[t] = s * (b[t] - lx);
+    } else if (MODE == MODE_PRES) {
+        const cx<T>* b = B.at(slot);
+        y[t] = (interior ? op.odC : jacobi_factor(op, i, j)) * (b[t] - lx);
+    } else if (MODE == MODE_PAPPLY) {
+        y[t] = (interior ? op.odC : jacobi_factor(op, i, j)) * lx;
     } else {  // MODE_JACOBI
         const cx<T>* b = B.at(slot);
         cx<T> r = b[t] - lx;
@@ -204,6 +209,12 @@ void stencil2d(hipStream_t st, const Op2<T>& op, int mode, T s, Vec<const cx<TI>
             break;
         case MODE_JACOBI0:
             k_stencil2d<T, TI, MODE_JACOBI0><<<grid, BS, 0, st>>>(op, s, X, B, Y, N, gx);
+            break;
+        case MODE_PRES:
+            k_stencil2d<T, TI, MODE_PRES><<<grid, BS, 0, st>>>(op, s, X, B, Y, N, gx);
+            break;
+        case MODE_PAPPLY:
+            k_stencil2d<T, TI, MODE_PAPPLY><<<grid, BS, 0, st>>>(op, s, X, B, Y, N, gx);
             break;
     }
 }

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(BS) void k_stencil3d(Op3<T> op, T s, Vec<const cx<T
     const int i = (int)(rem - (long long)j * sy);
     const bool interior = (i > 0) & (i < n) & (j > 0) & (j < n) & (l > 0) & (l < n);
     cx<T>* y = Y.at(slot);
-    if (MODE == MODE_JACOBI0) {
+    if (MODE == MODE_JACOBI0 || (MODE == MODE_PRES && !X.base)) {
         cx<T> f;
         if (interior) {
             f = op.odC;
@@ -120,6 +120,9 @@ __global__ __launch_bounds__(BS) void k_stencil3d(Op3<T> op, T s, Vec<const cx<T
         y[t] = lx;
     } else if (MODE == MODE_RESID) {
         y[t] = s * (B.at(slot)[t] - lx);
+    } else if (MODE == MODE_PRES || MODE == MODE_PAPPLY) {
+        const cx<T> f = interior ? op.odC : cdiv(mk(op.omega, (T)0), d);
+        y[t] = f * (MODE == MODE_PRES ? B.at(slot)[t] - lx : lx);
     } else {
         cx<T> r = B.at(slot)[t] - lx;
         cx<T> f = interior ? op.odC : cdiv(mk(op.omega, (T)0), d);
@@ -385,6 +388,13 @@ void stencil3d(hipStream_t st, const Op3<T>& op, int mode, T s, Vec<const cx<TI>
         case MODE_JACOBI: HELM_S3(MODE_JACOBI); break;
         case MODE_JACOBI0:
             k_stencil3d<T, TI, MODE_JACOBI0><<<dim3(gx * nslots), BS, 0, st>>>(op, s, X, B, Y, N, gx);
+            break;
+        // the preconditioned forms (GMRES smoothing) run one thread per node
+        case MODE_PRES:
+            k_stencil3d<T, TI, MODE_PRES><<<dim3(gx * nslots), BS, 0, st>>>(op, s, X, B, Y, N, gx);
+            break;
+        case MODE_PAPPLY:
+            k_stencil3d<T, TI, MODE_PAPPLY><<<dim3(gx * nslots), BS, 0, st>>>(op, s, X, B, Y, N, gx);
             break;
     }
 #undef HELM_S3

@@ -273,6 +273,52 @@ __global__ __launch_bounds__(BS) void k_update_solution(long long N, int m, cons
     x[t] = x[t] + acc;
 }
 
+// The small least-squares problem of m-step GMRES, one thread per slot:
+// minimise |beta e_1 - H y| over y in C^m for the (m+1) x m upper
+// Hessenberg H whose column j holds rows 0..j at hu[slot*hs + j*(m+1) + i]
+// (complex) and the subdiagonal h_{j+1,j} = hn[slot*(m+1) + j + 1] (real),
+// beta = hn[slot*(m+1)].  Givens rotations reduce H to upper triangular
+// form in place; back substitution gives y[slot*m + i].  A zero pivot (an
+// invariant Krylov space, or beta = 0) gives y_i = 0 for that column.
+constexpr int LSQ_MAX = 20;
+__global__ __launch_bounds__(WAVE) void k_gmres_lsq(int m, cxd* hu, int hs, const double* hn,
+                                                    cxd* y, int nslots) {
+    const int slot = blockIdx.x * WAVE + threadIdx.x;
+    if (slot >= nslots) return;
+    cxd* H = hu + (long long)slot * hs;
+    const double* sub = hn + (long long)slot * (m + 1);
+    cxd g[LSQ_MAX + 1], cs[LSQ_MAX], sn[LSQ_MAX];
+    g[0] = mk(sub[0], 0.0);
+    for (int j = 0; j < m; ++j) {
+        cxd* col = H + (long long)j * (m + 1);
+        for (int i = 0; i < j; ++i) {
+            const cxd a = col[i], b = col[i + 1];
+            col[i] = cs[i] * a + sn[i] * b;
+            col[i + 1] = mk(-sn[i].x, sn[i].y) * a + mk(cs[i].x, -cs[i].y) * b;
+        }
+        const cxd a = col[j];
+        const double b = sub[j + 1];
+        const double den = sqrt(a.x * a.x + a.y * a.y + b * b);
+        if (den == 0.0) {
+            cs[j] = mk(1.0, 0.0);
+            sn[j] = mk(0.0, 0.0);
+        } else {
+            cs[j] = mk(a.x / den, -a.y / den);
+            sn[j] = mk(b / den, 0.0);
+            col[j] = mk(den, 0.0);
+        }
+        g[j + 1] = mk(-sn[j].x, sn[j].y) * g[j];
+        g[j] = cs[j] * g[j];
+    }
+    cxd* ys = y + (long long)slot * m;
+    for (int i = m - 1; i >= 0; --i) {
+        cxd s = g[i];
+        for (int q = i + 1; q < m; ++q) s = s - H[(long long)q * (m + 1) + i] * ys[q];
+        const cxd d = H[(long long)i * (m + 1) + i];
+        ys[i] = (d.x == 0.0 && d.y == 0.0) ? mk(0.0, 0.0) : cdiv(s, d);
+    }
+}
+
 inline unsigned blocks(long long N) { return (unsigned)((N + BS - 1) / BS); }
 
 }  // namespace
@@ -302,6 +348,10 @@ void scale_inv(hipStream_t st, long long N, Vec<const cxd> X, Vec<cxd> Y, const 
                int div_stride, int nslots) {
     const unsigned gx = blocks(N);
     k_scale_inv<<<gx * nslots, BS, 0, st>>>(N, X, Y, div, div_stride, gx);
+}
+
+void gmres_lsq(hipStream_t st, int m, cxd* hu, int hs, const double* hn, cxd* y, int nslots) {
+    k_gmres_lsq<<<(unsigned)((nslots + WAVE - 1) / WAVE), WAVE, 0, st>>>(m, hu, hs, hn, y, nslots);
 }
 
 void real_to_complex(hipStream_t st, long long N, const double* f, cxd* b, int nslots) {

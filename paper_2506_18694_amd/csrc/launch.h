@@ -148,6 +148,9 @@ void norm2(hipStream_t st, long long N, Vec<const cxd> W, double* part, double* 
 template <typename TZ>
 void update_solution(hipStream_t st, long long N, int m, const int* mlen, Vec<const cx<TZ>> Z,
                      const cxd* y, int ystride, Vec<cxd> X, int nslots);
+// m-step GMRES least squares per slot (Hessenberg hu, norms hn, see
+// kernels_vec.hip); y[slot*m + i]; m <= 20
+void gmres_lsq(hipStream_t st, int m, cxd* hu, int hs, const double* hn, cxd* y, int nslots);
 // b = f (real -> complex)
 void real_to_complex(hipStream_t st, long long N, const double* f, cxd* b, int nslots);
 

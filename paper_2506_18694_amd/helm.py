@@ -18,6 +18,7 @@ HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV, HELM_ENOTSUP = 0,
 HELM_P1_TRI_RIGHT, HELM_Q1_HEX = 1, 2
 HELM_FP64, HELM_FP32_MG = 0, 1
 HELM_OUTER_FGMRES, HELM_OUTER_RICHARDSON = 0, 1
+HELM_CYCLE_V_JACOBI, HELM_CYCLE_W_GMRES = 0, 1
 OPS = {"B0": 0, "BDELTA": 1, "BSHIFT": 2, "L": 3, "N": 4, "H": 5, "M": 6}
 
 # every symbol include/helm.h declares
@@ -57,7 +58,8 @@ class helm_opts(ctypes.Structure):
                 ("no_graphs", ctypes.c_int), ("no_small", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("no_stream", ctypes.c_int),
                 ("full_reorth", ctypes.c_int), ("split", ctypes.c_int),
-                ("outer", ctypes.c_int)]
+                ("outer", ctypes.c_int), ("cycle", ctypes.c_int),
+                ("smooth_its", ctypes.c_int)]
 
 
 class helm_stats(ctypes.Structure):
@@ -169,7 +171,8 @@ class Solver:
                  restart=0, max_outer=0, hss_steps=0, hss_m=1, omega=2.0 / 3.0,
                  dirichlet_faces=0, profile=False, mg_cycles=0, graphs=True, small_kernel=True,
                  verbose=0, stream=None, streaming=True, split=False,
-                 full_reorth=False, outer="fgmres", x0_given=False):
+                 full_reorth=False, outer="fgmres", x0_given=False, cycle="v",
+                 smooth_its=0):
         import torch
         self.torch = torch
         L = lib()
@@ -189,6 +192,8 @@ class Solver:
         opts.full_reorth = 1 if full_reorth else 0
         opts.outer = {"fgmres": HELM_OUTER_FGMRES, "richardson": HELM_OUTER_RICHARDSON}[outer]
         opts.x0_given = 1 if x0_given else 0
+        opts.cycle = {"v": HELM_CYCLE_V_JACOBI, "w": HELM_CYCLE_W_GMRES}[cycle]
+        opts.smooth_its = int(smooth_its)
         self.x0_given = bool(x0_given)
         # the library's step count: hss_steps, else m * ceil(k)
         self.n_hss = int(hss_steps) if hss_steps > 0 else int(hss_m * math.ceil(float(k)))

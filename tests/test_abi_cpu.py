@@ -36,6 +36,7 @@ def test_strerror_and_defaults():
     L.helm_opts_default(ctypes.byref(o))
     assert (o.precision, o.nu1, o.nu2, o.hss_m, o.x0_given) == (0, 2, 2, 1, 0)
     assert o.outer == helm.HELM_OUTER_FGMRES
+    assert (o.cycle, o.smooth_its) == (helm.HELM_CYCLE_V_JACOBI, 0)
     assert abs(o.omega - 2.0 / 3.0) < 1e-15
 
 
@@ -72,6 +73,15 @@ def test_create_rejects_bad_options_and_unsupported():
     L.helm_opts_default(ctypes.byref(o))
     o.outer = 2
     assert _create(helm, L, opts=o)[0] == helm.HELM_EINVAL
+    L.helm_opts_default(ctypes.byref(o))
+    o.cycle = 2
+    assert _create(helm, L, opts=o)[0] == helm.HELM_EINVAL
+    L.helm_opts_default(ctypes.byref(o))
+    o.cycle, o.smooth_its = helm.HELM_CYCLE_W_GMRES, 21
+    assert _create(helm, L, opts=o)[0] == helm.HELM_EINVAL
+    L.helm_opts_default(ctypes.byref(o))
+    o.cycle, o.precision = helm.HELM_CYCLE_W_GMRES, helm.HELM_FP32_MG
+    assert _create(helm, L, opts=o)[0] == helm.HELM_ENOTSUP
     L.helm_opts_default(ctypes.byref(o))
     o.nu1 = 3
     assert _create(helm, L, opts=o)[0] == helm.HELM_ENOTSUP

@@ -1,0 +1,87 @@
+"""The paper's multigrid variant on the GPU (Sec. 5.3): a W-cycle whose
+smoother on every level, the coarsest included, is m iterations of
+Jacobi-left-preconditioned GMRES (m = 5 for the primal formulation), one
+cycle per HSS step, no coarse factorisation.
+
+Parity with the oracle's W-cycle (`oracle.multigrid.wcycle`), which builds
+the Krylov basis with modified Gram-Schmidt and solves the least-squares
+problem with numpy; the GPU uses classical Gram-Schmidt twice and Givens
+rotations on the device, so results agree to rounding (1e-10 relative):
+  * one cycle from zero in 2D and 3D, m = 5 and m = 3;
+  * the shifted-HSS preconditioner with one W-cycle per step;
+  * the FGMRES solve at the paper's k = 16 setting (counts within one, the
+    solution equal to the direct solve);
+  * the measured cycle contraction eta_mg equals the oracle's and is below
+    0.01 (the paper's measured rates are 0.0034 to 0.0006).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import multigrid, solver as osolver
+import workloads as W
+from gpu_util import to_dev, to_host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(dim, n, levels, k, dh, **kw):
+    from paper_2506_18694_amd import Solver
+    return Solver(dim, n, levels, k, 0.0, dh, cycle="w", **kw)
+
+
+@pytest.mark.parametrize("dim,n,levels,k,dh,its", [
+    (2, 64, 4, 16.0, 2.0, 5), (2, 48, 3, 7.0, 7.0, 3), (2, 184, 4, 32.0, 2.0, 5),
+    (3, 8, 3, 3.0, 3.0, 5), (3, 16, 2, 4.0, 2.0, 4)])
+def test_wcycle_matches_oracle(dim, n, levels, k, dh, its):
+    pr = osolver.Problem(dim, n, k, dh, levels=levels, cycles=1, cycle="w", smooth_its=its)
+    b = W.random_complex((2, pr.L.shape[0]), 41)
+    s = _gpu(dim, n, levels, k, dh, smooth_its=its, restart=4)
+    x = to_host(s.vcycle(to_dev(b)))
+    ref = np.stack([multigrid.wcycle(pr.hierarchy, bi, np.zeros_like(bi), 0, its) for bi in b])
+    assert rel_l2(x, ref) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n,levels,k,dh", [(2, 64, 4, 16.0, 2.0), (3, 8, 2, 3.0, 3.0)])
+def test_w_preconditioner_matches_oracle(dim, n, levels, k, dh):
+    pr = osolver.Problem(dim, n, k, dh, levels=levels, cycles=1, cycle="w")
+    v = W.random_complex((2, pr.L.shape[0]), 42)
+    s = _gpu(dim, n, levels, k, dh, restart=4)
+    z = to_host(s.precondition(to_dev(v)))
+    ref = np.stack([pr.precond(vi, inner="mg") for vi in v])
+    assert rel_l2(z, ref) < 1e-10
+
+
+def test_w_solve_at_paper_setting():
+    k, n, levels = 16.0, 64, 4
+    pr = osolver.Problem(2, n, k, 2.0, levels=levels, cycles=1, cycle="w")
+    r0 = pr.M @ W.box_source(n) - pr.B0 @ W.paper_initial_guess(pr.B0.shape[0], 3)
+    _, info = pr.solve(r0, tol=1e-6, inner="mg", restart=100, maxiter=100)
+    x, st = _gpu(2, n, levels, k, 2.0).solve(to_dev(r0[None]), tol=1e-6)
+    x = to_host(x)[0]
+    assert st["converged"] == 1 and st["mg_cycles"] == 1
+    assert abs(st["outer_its"] - info["its"]) <= 1, (st["outer_its"], info["its"])
+    assert np.linalg.norm(r0 - pr.B0 @ x) <= 1e-6 * 1.001 * np.linalg.norm(r0)
+    # the solution of B_0 e = r_0 to the tolerance (kappa(B_0) ~ 1e3 here)
+    assert rel_l2(x, pr.solve_direct(r0)) < 1e-3
+    assert abs(st["outer_rate"] - 0.2264) < 0.01
+
+
+def test_w_cycle_contraction_matches_oracle():
+    k, n, levels = 16.0, 64, 4
+    pr = osolver.Problem(2, n, k, 2.0, levels=levels, cycles=1, cycle="w")
+    b = W.random_complex(pr.L.shape[0], 43)
+    s = _gpu(2, n, levels, k, 2.0, restart=4)
+    x = to_host(s.vcycle(to_dev(b[None])))[0]
+    eta = np.linalg.norm(b - pr.L @ x) / np.linalg.norm(b)
+    xo = pr.mg_solve(b)
+    eta_o = np.linalg.norm(b - pr.L @ xo) / np.linalg.norm(b)
+    assert abs(eta - eta_o) < 1e-8 * eta_o
+    assert eta < 0.01
+
+
+def test_w_variant_has_no_coarse_solve():
+    from paper_2506_18694_amd.helm import HelmError
+    s = _gpu(2, 16, 2, 3.0, 3.0, restart=4)
+    with pytest.raises(HelmError):
+        s.coarse_solve(to_dev(W.random_complex(81, 44)))
