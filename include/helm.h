@@ -58,6 +58,16 @@ extern "C" {
 /* ---- mesh / element kinds ---------------------------------------------- */
 #define HELM_P1_TRI_RIGHT 1  /* 2D, right-diagonal P1 triangles */
 #define HELM_Q1_HEX       2  /* 3D, trilinear hexahedra          */
+#define HELM_MIXED_DG0_P1 3  /* 2D mixed formulation of Sec. 2: sigma in
+                                [DG0]^2, u in P1 on the right-diagonal mesh.
+                                Vectors are [u | sigma]: u at the N nodes,
+                                then sigma on the 2 n^2 triangles, triangle
+                                e = t n^2 + (p + n q) of cell (p, q) (t = 0:
+                                (p,q),(p+1,q),(p+1,q+1); t = 1:
+                                (p,q),(p+1,q+1),(p,q+1)), its x and y
+                                components at 2e and 2e + 1: N + 4 n^2
+                                complex values per column
+                                (helm_vector_length)                     */
 
 /* ---- precision modes ---------------------------------------------------- */
 #define HELM_FP64     0  /* everything in complex FP64                       */
@@ -89,6 +99,9 @@ extern "C" {
 #define HELM_OP_H       5  /* Gram matrix of the H_primal inner product
                               (Sec. 3.1) with delta_hat: 2 dh k M + k M_Gamma */
 #define HELM_OP_M       6  /* mass matrix                                    */
+#define HELM_OP_MIXED   7  /* mixed handles, level 0, FP64: the mixed
+                              operator A_delta on [u | sigma] (Sec. 2)      */
+#define HELM_OP_MIXED_SHIFT 8  /* mixed handles: A_delta_hat                */
 
 typedef struct helm_s helm_t;
 
@@ -131,7 +144,10 @@ typedef struct {
                           to T + E (I - T), still a contraction when
                           |E| < (1 - nu)/(1 + nu) = 1/k; the library measures
                           the V-cycle rate rho_V once (power iteration) and
-                          uses the smallest q >= 2 with rho_V^q <= 1/k.      */
+                          uses the smallest q >= 2 with rho_V^q <= 1/k
+                          (mixed form: <= 1/n, since sigma is recovered from
+                          the gradient of u, which magnifies a u error by
+                          ~1/(h k))                                          */
     int    no_graphs;  /* 1: launch the preconditioner's kernels one by one;
                           default 0 replays one captured HIP graph of the
                           whole HSS loop per application (captured on a
@@ -247,6 +263,10 @@ int helm_destroy(helm_t* h);
 
 /* Number of nodes N on the finest mesh, and on level l (0 = finest). */
 long long helm_nodes(const helm_t* h, int level);
+
+/* Complex values per column of rhs and x: N, or N + 4 n^2 for
+ * HELM_MIXED_DG0_P1 (-1 for NULL). */
+long long helm_vector_length(const helm_t* h);
 
 /*
  * Bytes of device workspace helm_solve / helm_precondition / helm_vcycle

@@ -69,6 +69,7 @@ class MixedProblem:
         self.E2 = self.G.shape[0]                  # 2 * triangles
         self.A0 = self.system(delta)
         self._lu = None
+        self._lm = None
 
     def system(self, delta):
         """A_delta as a sparse block matrix on [u | sigma]."""
@@ -118,13 +119,21 @@ class MixedProblem:
         s = dh - 1j
         return (self.K + (k * k * s * s) * self.M + (k * k * s) * self.MG).tocsr()
 
+    def _lmix_csr(self):
+        if self._lm is None:
+            self._lm = self.lmix()
+        return self._lm
+
     def hss_step_eliminated(self, U, R, solve_lmix):
         """The same step with sigma_{n+1} eliminated: from the sigma rows,
         k (dh - i) sigma' = grad u' + g with
         g = nu (k (dh + i) sigma + grad u) + c M_s^{-1} R_sigma;
         substituted into the u rows (and multiplied by k (dh - i)),
         Lmix u' = k (dh - i) [nu (k (dh + i) M u - G^T sigma + k M_Gamma u)
-                               + c R_u] - G^T g."""
+                               + c R_u] - G^T g.
+        The scalar solve is taken in correction form, u' = u + Lmix^{-1}
+        (rhs - Lmix u), as for the primal preconditioner (identical with an
+        exact solve; with multigrid it is a cycle warm-started at u)."""
         k, dh = self.k, self.delta_hat
         nu, c = (k - 1.0) / (k + 1.0), 2.0 * k / (k + 1.0)
         N = self.N
@@ -134,7 +143,7 @@ class MixedProblem:
         g = nu * (k * (dh + 1j) * sig + grad(u)) + c * Rs / self.ms
         ru = nu * (k * (dh + 1j) * (self.M @ u) - self.G.T @ sig + k * (self.MG @ u)) + c * Ru
         rhs = k * (dh - 1j) * ru - self.G.T @ g
-        u1 = solve_lmix(rhs)
+        u1 = u + solve_lmix(rhs - self._lmix_csr() @ u)
         s1 = (grad(u1) + g) / (k * (dh - 1j))
         return np.concatenate([u1, s1])
 

@@ -78,7 +78,7 @@ struct Engine {
         ws = static_cast<char*>(ws_);
         cap = cap_;
         R = h->restart;
-        N = h->Nl[0];
+        N = h->nv;  // column length (nodes, or nodes + triangle data when mixed)
         tol = tol_;
         s = h->stream;
         Lw = layout(h, cap);
@@ -144,6 +144,10 @@ struct Engine {
     }
 
     void apply_B(int mode, Vec<const cxd> X, Vec<const cxd> Bv, Vec<cxd> Y, int ns) {
+        if (h->mixed) {
+            mixed_system(h, h->delta, mode, X, Bv, Y, ns);
+            return;
+        }
         const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
         if (h->dim == 2)
             stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), mode, 1.0, X, Bv, Y, ns);
@@ -152,6 +156,12 @@ struct Engine {
                                       !h->opts.no_stream);
     }
     void apply_BZ(Vec<const cx<T>> Zv, Vec<cxd> Y, int ns) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (h->mixed) {
+                mixed_system(h, h->delta, MODE_APPLY, Zv, Vec<const cxd>{}, Y, ns);
+                return;
+            }
+        }
         const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
         if (h->dim == 2)
             stencil2d<double, T>(s, make_op2<double>(b0, h->n, h->omega), MODE_APPLY, 1.0, Zv,

@@ -232,7 +232,18 @@ struct helm_s {
     double prof_ms = 0.0, prof_bytes = 0.0, prof_pending_bytes = 0.0;
     long long prof_launches = 0;
 
-    Coef coef(int op) const { return op_coef(op, k, delta, dh); }
+    // mixed [DG0]^2 x P1 formulation (2D): the HSS inner operator becomes
+    // K + k^2 (dh - i)^2 M + k^2 (dh - i) M_Gamma (sigma eliminated)
+    bool mixed = false;
+    long long nv = 0;  // unknowns per column: N, or N + 4 n^2 (mixed)
+
+    Coef coef(int op) const {
+        if (mixed && op == HELM_OP_L) {
+            const zd s(dh, -1.0);
+            return Coef{1.0, k * k * s * s, k * k * s};
+        }
+        return op_coef(op, k, delta, dh);
+    }
 
     void prof_mark() {
         if (prof_used == prof_ev.size()) {
@@ -276,6 +287,7 @@ struct Layout {
     // per slot), its Hessenberg columns (two passes), norms, coefficients
     // and reduction partials
     size_t gk[32], ghu, ghu2, gn, gy, gpart, gnpart;
+    size_t mg;  // mixed: the per-step triangle data g of every slot
     size_t total;
 };
 
@@ -305,12 +317,15 @@ Layout layout(const helm_t* h, int nrhs) {
         L.mg_x[l] = take(smg * nrhs * h->Nl[l]);
         L.mg_t[l] = take(smg * nrhs * h->Nl[l]);
     }
-    L.R = take(smg * nrhs * N);
-    L.u = take(smg * nrhs * N);
-    L.V = take(sizeof(cxd) * (size_t)nrhs * (R + 1) * N);
-    L.Z = take(smg * (size_t)nrhs * R * N);
-    L.Bw = take(sizeof(cxd) * (size_t)nrhs * N);
-    L.Xw = take(sizeof(cxd) * (size_t)nrhs * N);
+    // column vectors: N unknowns, or N + 4 n^2 for the mixed formulation
+    const long long Nv = h->nv;
+    L.R = take(smg * nrhs * Nv);
+    L.u = take(smg * nrhs * Nv);
+    L.V = take(sizeof(cxd) * (size_t)nrhs * (R + 1) * Nv);
+    L.Z = take(smg * (size_t)nrhs * R * Nv);
+    L.Bw = take(sizeof(cxd) * (size_t)nrhs * Nv);
+    L.Xw = take(sizeof(cxd) * (size_t)nrhs * Nv);
+    L.mg = h->mixed ? take(sizeof(cxd) * (size_t)nrhs * (Nv - N)) : 0;
     if (h->opts.cycle == HELM_CYCLE_W_GMRES) {
         const int m = h->smooth_its;
         for (int l = 0; l < h->levels; ++l) L.gk[l] = take(sizeof(cxd) * (size_t)nrhs * (m + 1) * h->Nl[l]);
@@ -676,10 +691,61 @@ void hss_step_w(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
 
 inline bool w_variant(const helm_t* h) { return h->opts.cycle == HELM_CYCLE_W_GMRES; }
 
+// ---- the mixed formulation ([DG0]^2 x P1, 2D, FP64) ---------------------
+
+// Y = A_delta X (MODE_APPLY) or Y = B - A_delta X (MODE_RESID) for mixed
+// vectors [u | sigma]: u rows (delta - ik) M u + M_Gamma u + G^T sigma,
+// sigma rows (delta - ik) M_s sigma - G u.
+void mixed_system(helm_t* h, double delta, int mode, Vec<const cxd> X, Vec<const cxd> B, Vec<cxd> Y,
+                  int ns) {
+    const zd s(delta, -h->k);
+    const double sg = mode == MODE_RESID ? -1.0 : 1.0;
+    const Op2<double> op = make_op2<double>(Coef{0.0, sg * s, sg}, h->n, h->omega);
+    mixed_nodes(h->stream, op, mk(1.0, 0.0), mk(sg, 0.0), mk(0.0, 0.0), X,
+                mode == MODE_RESID ? B : Vec<const cxd>{}, Vec<const cxd>{}, Y, ns);
+    mixed_tris(h->stream, h->n, mode, mk(s.real(), s.imag()), X, B, Y, ns);
+}
+
+// One HSS step of the mixed shifted-HSS preconditioner with sigma
+// eliminated (correction form for u): with nu = (k-1)/(k+1), c = 2k/(k+1),
+// g = nu (k(dh+i) sigma + grad u) + c M_s^{-1} R_sigma (per triangle),
+// rho = k(dh-i) [nu (k(dh+i) M u - G^T sigma + k M_Gamma u) + c R_u]
+//       - G^T g - Lmix u,
+// e = q V-cycles on Lmix e = rho, u += e, sigma = (grad u + g) / (k(dh-i)).
+void hss_step_mixed(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
+    const long long N = h->Nl[0], Nv = h->nv;
+    const double k = h->k;
+    Vec<cxd> U = at_ws<cxd>(ws, Lw.u, Nv);
+    Vec<cxd> R = at_ws<cxd>(ws, Lw.R, Nv);
+    Vec<cxd> G = at_ws<cxd>(ws, Lw.mg, Nv - N);
+    Vec<cxd> rho = at_ws<cxd>(ws, Lw.mg_b[0], N);
+    Vec<cxd> e = at_ws<cxd>(ws, Lw.mg_x[0], N);
+    Vec<cxd> t = at_ws<cxd>(ws, Lw.mg_t[0], N);
+    const double nu = (k - 1.0) / (k + 1.0), c = 2.0 * k / (k + 1.0);
+    const zd kp = k * zd(h->dh, 1.0), km = k * zd(h->dh, -1.0);
+    if (s == 0) zero<double>(h->stream, U.base, Nv * ns);
+    mixed_g(h->stream, h->n, mk((nu * kp).real(), (nu * kp).imag()), nu, c, cst(U), cst(R), G, ns);
+    // k(dh-i) nu (k(dh+i) M + k M_Gamma) - Lmix as one stencil
+    const Coef lm = h->coef(HELM_OP_L);
+    const Coef comb{-lm.a, km * nu * kp - lm.b, km * nu * k - lm.c};
+    const zd sa = -km * nu, sb = km * c;
+    mixed_nodes(h->stream, make_op2<double>(comb, h->n, h->omega), mk(sb.real(), sb.imag()),
+                mk(sa.real(), sa.imag()), mk(-1.0, 0.0), cst(U), cst(R), cst(G), rho, ns);
+    vcycle<double>(h, Lw, ws, 0, cst(rho), e, t, ns);
+    for (int q = 1; q < h->cycles; ++q) vcycle<double>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
+    axpy1<double>(h->stream, N, 1.0, cst(e), U, ns);
+    const zd inv = 1.0 / km;
+    mixed_sigma(h->stream, h->n, mk(inv.real(), inv.imag()), cst(U), cst(G), U, ns);
+}
+
 // HSS step s of the handle's variant on the slot range described by L.
 template <typename T>
 void hss_step(helm_t* h, const Layout& L, void* ws, int ns, int s) {
     if constexpr (std::is_same<T, double>::value) {
+        if (h->mixed) {
+            hss_step_mixed(h, L, ws, ns, s);
+            return;
+        }
         if (w_variant(h)) {
             hss_step_w(h, L, ws, ns, s);
             return;
@@ -738,7 +804,8 @@ void hss_loop(helm_t* h, void* ws, const SlotGroup* g, int ng) {
 // a contraction when ||E|| (1 + nu) < 1 - nu, i.e. ||E|| < 1/k.  The V-cycle
 // rate rho_V is measured once per handle by power iteration on the cycle's
 // error map e <- e - V(L e) from a fixed pseudo-random start, and the
-// smallest q with rho_V^q <= 1/k is used (at least 2, at most 8).
+// smallest q with rho_V^q <= 1/k is used (at least 2, at most 8; 1/n for
+// the mixed form, see below).
 template <typename T>
 void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
     if (!h->cycles_auto || h->vrate > 0.0) return;
@@ -779,8 +846,11 @@ void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
     double rate = std::pow(norms[iters - 1] / norms[iters - 4], 1.0 / 3.0);
     if (!(rate > 0.0) || !std::isfinite(rate)) rate = 0.5;
     h->vrate = rate;
-    // ||T + E (I - T)|| <= nu + rho^q (1 + nu) < 1  <=>  rho^q < (1 - nu)/(1 + nu) = 1/k
-    const double bound = 1.0 / h->k;
+    // ||T + E (I - T)|| <= nu + rho^q (1 + nu) < 1  <=>  rho^q < (1 - nu)/(1 + nu) = 1/k.
+    // Mixed form: sigma' = (grad u' + g) / (k (dh - i)) turns an error e in u
+    // into one of size ~ |e| / (h k) in sigma, so the cycle error must be
+    // smaller by h k: rho^q < h = 1/n.
+    const double bound = h->mixed ? 1.0 / h->n : 1.0 / h->k;
     int q = 2;
     while (q < 8 && std::pow(rate, q) > bound) ++q;
     h->cycles = q;
@@ -790,11 +860,11 @@ void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
 // (FP64 v; z in the mode's storage type).
 template <typename T>
 void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<cx<T>> z, int ns) {
-    const long long N = h->Nl[0];
+    const long long N = h->nv;  // column length (the mixed vectors included)
     copy_cast<T, double>(h->stream, N, v, at_ws<cx<T>>(ws, Lw.R, N), ns);
     // optionally two slot groups on two streams when there are several columns
     // (not with the W variant, whose smoother buffers are not per group)
-    const int ng = (ns >= 2 && h->opts.split && !w_variant(h)) ? 2 : 1;
+    const int ng = (ns >= 2 && h->opts.split && !w_variant(h) && !h->mixed) ? 2 : 1;
     const int n0 = ng == 2 ? (ns + 1) / 2 : ns;
     SlotGroup grp[2] = {{Lw, n0, h->stream}, {shift_slots<T>(h, Lw, n0), ns - n0, h->aux_stream}};
     if (ng == 2) {
@@ -889,7 +959,7 @@ template <typename T>
 int solve_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws,
                   helm_stats* st) {
     const auto t0 = std::chrono::steady_clock::now();
-    const long long N = h->Nl[0];
+    const long long N = h->nv;
     Engine<T> E;
     struct Guard {
         Engine<T>& e;
@@ -973,7 +1043,7 @@ template <typename T>
 int richardson_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, void* ws,
                        helm_stats* st) {
     const auto t0 = std::chrono::steady_clock::now();
-    const long long N = h->Nl[0];
+    const long long N = h->nv;
     const Layout Lw = layout(h, nrhs);
     hipStream_t s = h->stream;
     char* w = static_cast<char*>(ws);
@@ -1034,7 +1104,9 @@ int richardson_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, 
         // r[q] = b[c] - B x[c] for the running columns c = run[q]
         const Vec<const cxd> Xr{x, N, 0, d_cols}, Br{rhs, N, 0, d_cols};
         const Vec<cxd> Rr{r, N, 0, nullptr};
-        if (h->dim == 2)
+        if (h->mixed)
+            mixed_system(h, h->delta, MODE_RESID, Xr, Br, Rr, nr);
+        else if (h->dim == 2)
             stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), MODE_RESID, 1.0, Xr,
                                       Br, Rr, nr);
         else
@@ -1133,7 +1205,7 @@ int richardson_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, 
 template <typename T>
 void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>> z, int ns,
                  double* res) {
-    const long long N = h->Nl[0];
+    const long long N = h->nv;
     hipStream_t s = h->stream;
     const int S = h->hss_steps;
     double* d_norm = reinterpret_cast<double*>(static_cast<char*>(ws) + Lw.dnorm);
@@ -1151,7 +1223,10 @@ void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>>
     SlotGroup g{Lw, ns, s};
     for (int step = 0; step < S; ++step) {
         hss_step<T>(h, g.L, ws, ns, step);
-        if (h->dim == 2)
+        if (h->mixed) {
+            if constexpr (std::is_same<T, double>::value)
+                mixed_system(h, h->dh, MODE_RESID, u, vv, rv, ns);
+        } else if (h->dim == 2)
             stencil2d<double, T>(s, make_op2<double>(cb, h->n, h->omega), MODE_RESID, 1.0, u, vv, rv,
                                  ns);
         else
@@ -1230,9 +1305,10 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
     helm_opts o;
     if (opts) o = *opts; else helm_opts_default(&o);
     if (mesh->dim != 2 && mesh->dim != 3) return HELM_EINVAL;
-    if ((mesh->dim == 2 && mesh->elem != HELM_P1_TRI_RIGHT) ||
+    if ((mesh->dim == 2 && mesh->elem != HELM_P1_TRI_RIGHT && mesh->elem != HELM_MIXED_DG0_P1) ||
         (mesh->dim == 3 && mesh->elem != HELM_Q1_HEX))
         return HELM_EINVAL;
+    const bool mixed = mesh->elem == HELM_MIXED_DG0_P1;
     if (mesh->n < 2 || mesh->levels < 1 || mesh->levels > 30) return HELM_EINVAL;
     if (mesh->n % (1 << (mesh->levels - 1)) != 0) return HELM_EINVAL;
     if (!(k > 0.0) || !std::isfinite(k)) return HELM_EINVAL;
@@ -1249,6 +1325,8 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
     if (bc && bc->dirichlet_faces != 0) return HELM_ENOTSUP;
     if (!wvar && (o.nu1 != 2 || o.nu2 != 2)) return HELM_ENOTSUP;
     if (wvar && o.precision != HELM_FP64) return HELM_ENOTSUP;
+    // the mixed formulation: FP64, V cycles
+    if (mixed && (o.precision != HELM_FP64 || wvar)) return HELM_ENOTSUP;
     const int nc_side = mesh->n >> (mesh->levels - 1);
     long long ncoarse = 1;
     for (int d = 0; d < mesh->dim; ++d) ncoarse *= (nc_side + 1);
@@ -1288,6 +1366,8 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
             h->nl.push_back(nl);
             h->Nl.push_back(Nl);
         }
+        h->mixed = mixed;
+        h->nv = h->Nl[0] + (mixed ? 4LL * h->n * h->n : 0);
         // coarsest-mesh dense L (from the same stencil rows the kernels use);
         // the W variant smooths on the coarsest mesh instead
         const int ncs = h->nl.back();
@@ -1376,6 +1456,8 @@ int helm_destroy(helm_t* h) {
     return rc;
 }
 
+long long helm_vector_length(const helm_t* h) { return h ? h->nv : -1; }
+
 long long helm_nodes(const helm_t* h, int level) {
     if (!h || level < 0 || level >= h->levels) return -1;
     return h->Nl[level];
@@ -1418,6 +1500,16 @@ int helm_load_nodal(helm_t* h, const double* f_nodal, void* b, int nrhs) {
     try {
         HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(cxd) * N * nrhs, h->stream));
         real_to_complex(h->stream, N, f_nodal, tmp, nrhs);
+        if (h->mixed) {
+            // F_u = M f / (delta - ik), F_sigma = 0 (the mixed right-hand side of Sec. 2)
+            const long long Nv = h->nv;
+            cxd* bp = static_cast<cxd*>(b);
+            const Coef cf{0.0, 1.0 / zd(h->delta, -h->k), 0.0};
+            stencil2d<double, double>(h->stream, make_op2<double>(cf, h->n, h->omega), MODE_APPLY, 1.0,
+                                      Vec<const cxd>{tmp, N, 0, nullptr}, Vec<const cxd>{},
+                                      Vec<cxd>{bp, Nv, 0, nullptr}, nrhs);
+            for (int c = 0; c < nrhs; ++c) zero<double>(h->stream, bp + (long long)c * Nv + N, Nv - N);
+        } else
         apply_mode<double>(h, HELM_OP_M, 0, MODE_APPLY, 1.0, Vec<const cxd>{tmp, N, 0, nullptr},
                            Vec<const cxd>{}, Vec<cxd>{static_cast<cxd*>(b), N, 0, nullptr}, nrhs);
         HIPCHK(hipFreeAsync(tmp, h->stream));
@@ -1433,6 +1525,19 @@ int helm_load_nodal(helm_t* h, const double* f_nodal, void* b, int nrhs) {
 
 int helm_apply(helm_t* h, int op, int level, int prec, const void* x, void* y, int nrhs) {
     if (!h || !x || !y || nrhs < 1 || level < 0 || level >= h->levels) return HELM_EINVAL;
+    if (op == HELM_OP_MIXED || op == HELM_OP_MIXED_SHIFT) {
+        if (!h->mixed || level != 0 || prec != HELM_FP64) return HELM_EINVAL;
+        const long long Nv = h->nv;
+        try {
+            mixed_system(h, op == HELM_OP_MIXED ? h->delta : h->dh, MODE_APPLY,
+                         Vec<const cxd>{static_cast<const cxd*>(x), Nv, 0, nullptr}, Vec<const cxd>{},
+                         Vec<cxd>{static_cast<cxd*>(y), Nv, 0, nullptr}, nrhs);
+            HIPCHK(hipGetLastError());
+        } catch (const DevErr&) {
+            return HELM_EDEVICE;
+        }
+        return HELM_OK;
+    }
     if (op < HELM_OP_B0 || op > HELM_OP_M) return HELM_EINVAL;
     if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
     const long long N = h->Nl[level];
@@ -1600,7 +1705,7 @@ int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs, void* wor
 
 int helm_precondition(helm_t* h, const void* v, void* z, int nrhs, void* workspace) {
     if (!h || !v || !z || !workspace || nrhs < 1) return HELM_EINVAL;
-    const long long N = h->Nl[0];
+    const long long N = h->nv;
     const Layout Lw = layout(h, nrhs);
     try {
         Vec<const cxd> vv{static_cast<const cxd*>(v), N, 0, nullptr};
@@ -1623,7 +1728,7 @@ int helm_precondition(helm_t* h, const void* v, void* z, int nrhs, void* workspa
 
 int helm_hss_history(helm_t* h, const void* v, void* z, int nrhs, void* workspace, double* res) {
     if (!h || !v || !z || !workspace || !res || nrhs < 1) return HELM_EINVAL;
-    const long long N = h->Nl[0];
+    const long long N = h->nv;
     const Layout Lw = layout(h, nrhs);
     const cxd* vp = static_cast<const cxd*>(v);
     try {

@@ -15,14 +15,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhelm.so")
 
 HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_ENOCONV, HELM_ENOTSUP = 0, -1, -2, -3, -4, -5
-HELM_P1_TRI_RIGHT, HELM_Q1_HEX = 1, 2
+HELM_P1_TRI_RIGHT, HELM_Q1_HEX, HELM_MIXED_DG0_P1 = 1, 2, 3
 HELM_FP64, HELM_FP32_MG = 0, 1
 HELM_OUTER_FGMRES, HELM_OUTER_RICHARDSON = 0, 1
 HELM_CYCLE_V_JACOBI, HELM_CYCLE_W_GMRES = 0, 1
-OPS = {"B0": 0, "BDELTA": 1, "BSHIFT": 2, "L": 3, "N": 4, "H": 5, "M": 6}
+OPS = {"B0": 0, "BDELTA": 1, "BSHIFT": 2, "L": 3, "N": 4, "H": 5, "M": 6, "MIXED": 7,
+       "MIXED_SHIFT": 8}
 
 # every symbol include/helm.h declares
 EXPORTS = ("helm_opts_default", "helm_strerror", "helm_create", "helm_destroy", "helm_nodes",
+           "helm_vector_length",
            "helm_workspace_bytes", "helm_solve", "helm_load_nodal", "helm_apply",
            "helm_hss_residual", "helm_jacobi", "helm_restrict_residual", "helm_prolong_correct",
            "helm_coarse_solve", "helm_vcycle", "helm_precondition", "helm_hss_history",
@@ -112,6 +114,7 @@ def lib():
                             ctypes.POINTER(helm_opts), P, ctypes.POINTER(P)]),
         "helm_destroy": (I, [P]),
         "helm_nodes": (ctypes.c_longlong, [P, I]),
+        "helm_vector_length": (ctypes.c_longlong, [P]),
         "helm_workspace_bytes": (I, [P, I, ctypes.POINTER(ctypes.c_size_t)]),
         "helm_solve": (I, [P, P, P, I, D, P, ctypes.POINTER(helm_stats)]),
         "helm_load_nodal": (I, [P, P, P, I]),
@@ -172,11 +175,12 @@ class Solver:
                  dirichlet_faces=0, profile=False, mg_cycles=0, graphs=True, small_kernel=True,
                  verbose=0, stream=None, streaming=True, split=False,
                  full_reorth=False, outer="fgmres", x0_given=False, cycle="v",
-                 smooth_its=0):
+                 smooth_its=0, mixed=False):
         import torch
         self.torch = torch
         L = lib()
-        mesh = helm_mesh(dim, HELM_P1_TRI_RIGHT if dim == 2 else HELM_Q1_HEX, n, levels)
+        elem = HELM_Q1_HEX if dim == 3 else (HELM_MIXED_DG0_P1 if mixed else HELM_P1_TRI_RIGHT)
+        mesh = helm_mesh(dim, elem, n, levels)
         opts = helm_opts()
         L.helm_opts_default(ctypes.byref(opts))
         opts.precision = HELM_FP64 if precision == "fp64" else HELM_FP32_MG
@@ -212,6 +216,8 @@ class Solver:
         self.precision = precision
         self.prec_code = opts.precision
         self.N = self.nodes(0)
+        self.mixed = bool(mixed)
+        self.NV = int(L.helm_vector_length(self.h))  # column length of rhs / x
         self._ws = {}
 
     # -- lifetime -----------------------------------------------------------
@@ -270,11 +276,11 @@ class Solver:
         (x, stats dict).  x0: initial guess (copied into x; needs a solver
         built with x0_given=True, which otherwise starts from 0)."""
         torch = self.torch
-        self._check_vec(rhs, self.N, torch.complex128, "rhs")
+        self._check_vec(rhs, self.NV, torch.complex128, "rhs")
         nrhs = self._cols(rhs)
         if x is None:
             x = torch.empty_like(rhs)
-        self._check_vec(x, self.N, torch.complex128, "x")
+        self._check_vec(x, self.NV, torch.complex128, "x")
         if x0 is not None:
             if not self.x0_given:
                 raise ValueError("x0 needs a Solver built with x0_given=True")
@@ -292,19 +298,22 @@ class Solver:
         return x, d
 
     def load_nodal(self, f):
-        """b = M f for real FP64 nodal values f (nrhs, N) on the device."""
+        """b = M f for real FP64 nodal values f (nrhs, N) on the device; on a
+        mixed handle the mixed right-hand side [M f / (delta - ik) | 0]."""
         torch = self.torch
         if f.dtype != torch.float64 or f.device.type != "cuda" or not f.is_contiguous():
             raise ValueError("f must be a contiguous float64 CUDA tensor")
         nrhs = self._cols(f)
-        b = torch.empty(f.shape, dtype=torch.complex128, device=f.device)
+        shape = f.shape[:-1] + (self.NV,)
+        b = torch.empty(shape, dtype=torch.complex128, device=f.device)
         _check(lib().helm_load_nodal(self.h, _ptr(f), _ptr(b), nrhs), "helm_load_nodal")
         return b
 
     # -- the individual steps ------------------------------------------------------
     def apply(self, op, x, level=0, prec=None):
         p = self._prec(prec)
-        self._check_vec(x, self.nodes(level), self._vec_dtype(p), "x")
+        n_len = self.NV if op.startswith("MIXED") else self.nodes(level)
+        self._check_vec(x, n_len, self._vec_dtype(p), "x")
         y = self.torch.empty_like(x)
         _check(lib().helm_apply(self.h, OPS[op], level, p, _ptr(x), _ptr(y), self._cols(x)),
                "helm_apply")
@@ -363,7 +372,7 @@ class Solver:
         ||v_c - B_shift u_s|| after HSS step s (res[c, 0] = ||v_c||), a
         float64 numpy array (nrhs, hss_steps + 1)."""
         import numpy as np
-        self._check_vec(v, self.N, self.torch.complex128, "v")
+        self._check_vec(v, self.NV, self.torch.complex128, "v")
         z = self.torch.empty_like(v)
         nrhs = self._cols(v)
         steps = self.n_hss
@@ -374,7 +383,7 @@ class Solver:
         return z, res
 
     def precondition(self, v):
-        self._check_vec(v, self.N, self.torch.complex128, "v")
+        self._check_vec(v, self.NV, self.torch.complex128, "v")
         z = self.torch.empty_like(v)
         nrhs = self._cols(v)
         _check(lib().helm_precondition(self.h, _ptr(v), _ptr(z), nrhs,
