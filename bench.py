@@ -203,7 +203,16 @@ PAPER_MG = {16.0: {"fgmres": {0.5: 29, 1.0: 8, 1.5: 6}, "eta_s": 0.8778, "eta_h"
             128.0: {"fgmres": {0.5: 66, 1.0: 6, 1.5: 2}, "eta_s": 0.9844, "eta_h": 0.1130}}
 
 
-def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "richardson"), seed=3):
+# the same for the mixed formulation (two W-cycles with GMRES(4) smoothing
+# per HSS step in the paper)
+PAPER_MG_MIXED = {16.0: {"fgmres": {0.5: 38, 1.0: 9, 1.5: 7}, "eta_s": 0.8806, "eta_h": 0.2830},
+                  32.0: {"fgmres": {0.5: 50, 1.0: 8, 1.5: 6}, "eta_s": 0.9373, "eta_h": 0.2386},
+                  64.0: {"fgmres": {0.5: 72, 1.0: 8, 1.5: 5}, "eta_s": 0.9687, "eta_h": 0.2083},
+                  128.0: {"fgmres": {0.5: 85, 1.0: 7, 1.5: 3}, "eta_s": 0.9842, "eta_h": 0.1796}}
+
+
+def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "richardson"), seed=3,
+              form="primal"):
     """The paper's experiment of Sec. 5.3 on the GPU path: delta_hat = 2,
     c0 k^(3/2) cells, uniform and box sources, seeded random initial guess,
     relative tolerance 1e-6, ceil(k^theta) HSS steps for theta in
@@ -216,7 +225,9 @@ def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "ric
     iterates as the solve from x_0).  cycle "w" runs the paper's own
     multigrid (one W-cycle per HSS step, GMRES(5)-Jacobi smoothing on 4
     levels) instead of the library's V(2,2) Jacobi cycles, and reports the
-    cycle's residual contraction eta_mg on a random right-hand side."""
+    cycle's residual contraction eta_mg on a random right-hand side.  form
+    "mixed" solves the mixed [DG0]^2 x P1 system instead (sigma eliminated
+    in every HSS step)."""
     import math
     import torch
     from paper_2506_18694_amd import Solver
@@ -226,21 +237,24 @@ def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "ric
         if cycle == "w":
             levels = 4  # the paper's hierarchy: 4 levels, 64x fewer coarsest DoFs
         N = (n + 1) ** 2
-        x0 = torch.from_numpy(W.paper_initial_guess(N, seed)).to("cuda").reshape(1, N)
+        NV = N + (4 * n * n if form == "mixed" else 0)
+        x0 = torch.from_numpy(W.paper_initial_guess(NV, seed)).to("cuda").reshape(1, NV)
+        mix = form == "mixed"
+        sys_op = "MIXED" if mix else "B0"
         for source in ("uniform", "box"):
             f = W.uniform_source(2, n) if source == "uniform" else W.box_source(n)
-            row = {"k": k, "n": n, "levels": levels, "dofs": N, "source": source}
+            row = {"k": k, "n": n, "levels": levels, "dofs": NV, "source": source, "form": form}
             for theta in (0.5, 1.0, 1.5):
                 steps = int(math.ceil(k ** theta))
                 for outer in outers:
                     t0 = time.perf_counter()
                     s = Solver(2, n, levels, k, 0.0, 2.0, precision=precision, hss_steps=steps,
                                outer=outer, x0_given=rtol_ref == "b",
-                               restart=200 if outer == "fgmres" else 0, max_outer=2000,
-                               cycle=cycle)
+                               restart=(120 if mix else 200) if outer == "fgmres" else 0,
+                               max_outer=2000, cycle=cycle, mixed=mix)
                     b = s.load_nodal(torch.from_numpy(f).to("cuda").reshape(1, N))
                     if rtol_ref == "r0":
-                        x, st = s.solve((b - s.apply("B0", x0)).contiguous(), tol=1e-6)
+                        x, st = s.solve((b - s.apply(sys_op, x0)).contiguous(), tol=1e-6)
                     else:
                         x, st = s.solve(b, tol=1e-6, x0=x0)
                     torch.cuda.synchronize()
@@ -253,7 +267,7 @@ def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "ric
                         % (k, source, key, st["outer_its"], st["mg_cycles"], st["outer_rate"],
                            time.perf_counter() - t0))
                     if theta == 1.0 and outer == "fgmres":
-                        R = b - s.apply("B0", x0)
+                        R = b - s.apply(sys_op, x0)
                         _, res = s.hss_history(R.contiguous())
                         row["eta_s"] = float((res[0, -1] / res[0, 0]) ** (1.0 / steps))
                         # one cycle on a random right-hand side: residual contraction
@@ -264,8 +278,9 @@ def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "ric
                                               torch.linalg.vector_norm(rb))
                     s.close()
             row["nu_s"] = (k - 1.0) / (k + 1.0)
-            row["paper_mg"] = {"fgmres_uniform": {str(t): c for t, c in PAPER_MG[k]["fgmres"].items()},
-                               "eta_s": PAPER_MG[k]["eta_s"], "eta_h": PAPER_MG[k]["eta_h"]}
+            ref = PAPER_MG_MIXED if mix else PAPER_MG
+            row["paper_mg"] = {"fgmres_uniform": {str(t): c for t, c in ref[k]["fgmres"].items()},
+                               "eta_s": ref[k]["eta_s"], "eta_h": ref[k]["eta_h"]}
             rows.append(row)
     return rows
 
@@ -304,6 +319,7 @@ def main():
                     help="v: the library's V(2,2) Jacobi cycles; w: the paper's W-cycle with "
                          "GMRES(5)-Jacobi smoothing on 4 levels")
     ap.add_argument("--paper-outer", default="fgmres,richardson")
+    ap.add_argument("--paper-form", choices=("primal", "mixed"), default="primal")
     ap.add_argument("--paper-rtol", choices=("r0", "b"), default="r0",
                     help="the 1e-6 tolerance relative to the initial residual (r0) or to |b|")
     args = ap.parse_args()
@@ -321,7 +337,7 @@ def main():
         ks = [float(v) for v in args.paper_k.split(",")]
         t0 = time.perf_counter()
         rows = run_paper(W, ks, args.paper_precision, args.paper_rtol, args.paper_cycle,
-                         tuple(args.paper_outer.split(",")))
+                         tuple(args.paper_outer.split(",")), form=args.paper_form)
         out = {"metric": "outer iterations and measured rates at the paper's settings",
                "value": None, "unit": "iterations", "n_gpus": 1, "steps": 1, "warmup": 0,
                "ms_per_step": (time.perf_counter() - t0) * 1e3, "higher_is_better": False,
@@ -330,6 +346,7 @@ def main():
                "data": "synthetic",
                "config": {"workload": "paper-2d-p1-delta_hat2", "tol": 1e-6,
                           "tol_relative_to": args.paper_rtol, "cycle": args.paper_cycle,
+                          "form": args.paper_form,
                           "precision": args.paper_precision},
                "table": rows}
         print(json.dumps(out), flush=True)

@@ -210,10 +210,14 @@ struct helm_s {
 
     // captured HIP graphs of the preconditioner's HSS loop, per workspace,
     // slot count, precision and cycle count; captured on cap_stream
+    // the loop is captured as a head graph (step 0 and the remainder steps)
+    // and a body graph of `block` steps replayed `reps` times, so that no
+    // graph holds more than ~20000 launches
     struct GraphEntry {
         void* ws;
         int s0, ns, tag, cycles;
-        hipGraphExec_t exec;
+        hipGraphExec_t head, body;
+        int reps;
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
@@ -783,13 +787,14 @@ Layout shift_slots(const helm_t* h, const Layout& Lw, int s0) {
 // streams advance together and one group's finest-level passes overlap
 // another's latency-bound coarse levels.
 template <typename T>
-void hss_loop(helm_t* h, void* ws, const SlotGroup* g, int ng) {
+void hss_loop(helm_t* h, void* ws, const SlotGroup* g, int ng, int s_begin = 0, int s_end = -1) {
     struct Restore {
         helm_t* h;
         hipStream_t st;
         ~Restore() { h->stream = st; }
     } restore{h, h->stream};
-    for (int s = 0; s < h->hss_steps; ++s) {
+    if (s_end < 0) s_end = h->hss_steps;
+    for (int s = s_begin; s < s_end; ++s) {
         for (int q = 0; q < ng; ++q) {
             h->stream = g[q].st;
             hss_step<T>(h, g[q].L, ws, g[q].ns, s);
@@ -856,6 +861,35 @@ void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
     h->cycles = q;
 }
 
+// Capture HSS steps [s_begin, s_end) of one slot group on the capture
+// stream.  Returns the graph (caller destroys it).
+template <typename T>
+hipGraph_t capture_steps(helm_t* h, void* ws, const SlotGroup& g, int s_begin, int s_end) {
+    hipGraph_t graph = nullptr;
+    SlotGroup cg = g;
+    cg.st = h->cap_stream;
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        hss_loop<T>(h, ws, &cg, 1, s_begin, s_end);
+    } catch (...) {
+        (void)hipStreamEndCapture(h->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(h->cap_stream, &graph));
+    return graph;
+}
+
+template <typename T>
+hipGraphExec_t instantiate_steps(helm_t* h, void* ws, const SlotGroup& g, int s_begin, int s_end) {
+    hipGraph_t graph = capture_steps<T>(h, ws, g, s_begin, s_end);
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+    return ex;
+}
+
 // z = B~^{-1} v for ns slots: v and z addressed through Vec descriptors
 // (FP64 v; z in the mode's storage type).
 template <typename T>
@@ -876,18 +910,21 @@ void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<c
     if (h->prof_on || h->opts.no_graphs || w_variant(h)) {
         hss_loop<T>(h, ws, grp, ng);
     } else {
-        // each group's whole HSS loop (all steps, cycles and levels) is
-        // replayed as one captured HIP graph; it reads R and writes u at fixed
-        // workspace addresses, so one graph serves every outer iteration
+        // each group's HSS loop (all steps, cycles and levels) is replayed
+        // from captured HIP graphs; it reads R and writes u at fixed
+        // workspace addresses, so the graphs serve every outer iteration.
+        // A loop of up to ~20000 launches is one graph; a longer one is a
+        // head graph (step 0 and the remainder) and a body graph of a block
+        // of steps replayed several times (steps s > 0 launch the same work)
         const int tag = (int)sizeof(T);
         for (int q = 0; q < ng; ++q) {
             const int s0 = q == 0 ? 0 : n0;
-            hipGraphExec_t ex = nullptr;
+            const helm_s::GraphEntry* ge = nullptr;
             for (const auto& e : h->graphs)
                 if (e.ws == ws && e.s0 == s0 && e.ns == grp[q].ns && e.tag == tag &&
                     e.cycles == h->cycles)
-                    ex = e.exec;
-            if (!ex) {
+                    ge = &e;
+            if (!ge) {
                 // run the first two steps eagerly before capturing, so that
                 // the launches that measure their best tiling do so (the
                 // captured loop recomputes everything from step 0)
@@ -902,25 +939,38 @@ void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<c
                         hss_step<T>(h, grp[q].L, ws, grp[q].ns, s);
                     }
                 }
-                hipGraph_t graph = nullptr;
-                SlotGroup cg = grp[q];
-                cg.st = h->cap_stream;
-                HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-                try {
-                    hss_loop<T>(h, ws, &cg, 1);
-                } catch (...) {
-                    (void)hipStreamEndCapture(h->cap_stream, &graph);
-                    if (graph) (void)hipGraphDestroy(graph);
-                    throw;
+                const int S = h->hss_steps;
+                int head = S, block = 0, reps = 0;
+                if (S >= 2) {
+                    // launches of one step s > 0
+                    hipGraph_t one = capture_steps<T>(h, ws, grp[q], 1, 2);
+                    size_t n1 = 0;
+                    const hipError_t e = hipGraphGetNodes(one, nullptr, &n1);
+                    (void)hipGraphDestroy(one);
+                    HIPCHK(e);
+                    const size_t limit = 20000;
+                    block = (int)std::max<size_t>(1, limit / std::max<size_t>(1, n1));
+                    if (S - 1 > block) {
+                        const int r = (S - 1) % block;
+                        head = 1 + r;
+                        reps = (S - 1 - r) / block;
+                    }
                 }
-                hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
-                HIPCHK(e);
-                e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                HIPCHK(e);
-                h->graphs.push_back(helm_s::GraphEntry{ws, s0, grp[q].ns, tag, h->cycles, ex});
+                helm_s::GraphEntry ne{ws, s0, grp[q].ns, tag, h->cycles, nullptr, nullptr, reps};
+                ne.head = instantiate_steps<T>(h, ws, grp[q], 0, head);
+                if (reps > 0) {
+                    try {
+                        ne.body = instantiate_steps<T>(h, ws, grp[q], head, head + block);
+                    } catch (...) {
+                        (void)hipGraphExecDestroy(ne.head);
+                        throw;
+                    }
+                }
+                h->graphs.push_back(ne);
+                ge = &h->graphs.back();
             }
-            HIPCHK(hipGraphLaunch(ex, grp[q].st));
+            HIPCHK(hipGraphLaunch(ge->head, grp[q].st));
+            for (int r = 0; r < ge->reps; ++r) HIPCHK(hipGraphLaunch(ge->body, grp[q].st));
         }
     }
     if (ng == 2) {
@@ -1450,7 +1500,10 @@ int helm_destroy(helm_t* h) {
     if (h->d_cinv && hipFree(h->d_cinv) != hipSuccess) rc = HELM_EDEVICE;
     h->d_cinv = nullptr;
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
-    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto& g : h->graphs) {
+        (void)hipGraphExecDestroy(g.head);
+        if (g.body) (void)hipGraphExecDestroy(g.body);
+    }
     release_handle_objects(h);
     delete h;
     return rc;

@@ -111,3 +111,21 @@ def test_paper_mixed_rate_at_k16():
     _, st = _gpu(n, 3, k, dh, mg_cycles=4).solve(to_dev(r0[None]), tol=1e-6)
     assert st["converged"] == 1
     assert abs(st["outer_rate"] - 0.2806) < 0.01, st["outer_rate"]
+
+
+@pytest.mark.parametrize("mixed_form,n,levels,k,steps", [(True, 32, 3, 8.0, 1500),
+                                                         (False, 32, 2, 4.0, 4000)])
+def test_long_hss_loop_graphs_equal_eager(mixed_form, n, levels, k, steps):
+    """A preconditioner whose HSS loop launches more work than one captured
+    graph holds (~20000 launches) is replayed as a head graph plus a body
+    graph of a block of steps launched several times: the result equals the
+    eager launches bit for bit."""
+    from paper_2506_18694_amd import Solver
+    outs = []
+    for graphs in (True, False):
+        s = Solver(2, n, levels, k, 0.0, 2.0, mixed=mixed_form, hss_steps=steps, mg_cycles=2,
+                   restart=4, graphs=graphs)
+        v = W.random_complex((2, s.NV), 54)
+        outs.append(to_host(s.precondition(to_dev(v))))
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
