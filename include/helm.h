@@ -25,6 +25,9 @@
  * Data layout (all vectors): complex, interleaved (re, im), one column per
  * right-hand side, column-major [nrhs][N]; nodes lexicographic,
  * node (i, j[, l]) at index i + (n+1) (j + (n+1) l), N = (n+1)^dim.
+ * The mixed element (HELM_MIXED_DG0_P1) appends the triangle values of
+ * sigma to every column of rhs, x and the preconditioner's vectors:
+ * columns of helm_vector_length(h) = N + 4 n^2 values.
  * FP64 vectors are double2, FP32 vectors float2.  Every vector pointer
  * passed to this library is a DEVICE pointer on the device current when
  * helm_create was called; the caller owns it and it is not retained after
@@ -278,9 +281,10 @@ int helm_workspace_bytes(const helm_t* h, int nrhs, size_t* bytes);
  * Solve B_delta x = rhs for nrhs columns (B_0 when delta = 0), to
  * ||rhs - B x||_2 <= tol ||rhs||_2 per column (Sec. 5.1's relative
  * tolerance; the true residual is recomputed in FP64 at the end).
- *   rhs, x: device, complex FP64 [nrhs][N]; rhs is an assembled load vector
- *     (the preconditioner maps the dual space to the primal space,
- *     Sec. 4), e.g. from helm_load_nodal.
+ *   rhs, x: device, complex FP64 [nrhs][helm_vector_length(h)]; rhs is an
+ *     assembled load vector (the preconditioner maps the dual space to the
+ *     primal space, Sec. 4), e.g. from helm_load_nodal.  Mixed element:
+ *     the mixed system A_delta [u | sigma] = rhs.
  *   workspace: device, helm_workspace_bytes(h, nrhs) bytes.
  *   stats: may be NULL.
  * Returns HELM_OK, or HELM_ENOCONV with x holding the last iterate when
@@ -292,7 +296,9 @@ int helm_solve(helm_t* h, const void* rhs, void* x, int nrhs, double tol,
 
 /*
  * b = M f for nodal source values f (real FP64 [nrhs][N]): the load vector
- * of the nodal interpolant of f.  b: device complex FP64 [nrhs][N].
+ * of the nodal interpolant of f.  b: device complex FP64 [nrhs][N]; for the
+ * mixed element b = [M f / (delta - ik) | 0], [nrhs][N + 4 n^2] (the mixed
+ * right-hand side of Sec. 2).
  */
 int helm_load_nodal(helm_t* h, const double* f_nodal, void* b, int nrhs);
 
@@ -336,13 +342,16 @@ int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs,
 
 /* Shifted-HSS preconditioner z = B~^{-1} v (Definition "Shifted HSS
  * iteration for the primal system"), correction form, in the handle's
- * precision mode.  v, z: complex FP64 [nrhs][N]. */
+ * precision mode.  v, z: complex FP64 [nrhs][helm_vector_length(h)]; the
+ * mixed element applies the mixed preconditioner (Definition "Shifted HSS
+ * preconditioner for the mixed system", sigma eliminated in every step). */
 int helm_precondition(helm_t* h, const void* v, void* z, int nrhs,
                       void* workspace);
 
 /* The preconditioner of helm_precondition with the HSS residual recorded:
  * after HSS step s (s = 1 .. hss_steps) of column c,
- *   res[c * (hss_steps + 1) + s] = ||v_c - B_shift u_s||_2,
+ *   res[c * (hss_steps + 1) + s] = ||v_c - B_shift u_s||_2
+ * (the mixed element: ||v_c - A_delta_hat U_s||_2),
  * and res[c * (hss_steps + 1)] = ||v_c||_2, all in FP64 arithmetic on the
  * iterate u_s in the handle's precision mode (the residual contraction of
  * the HSS iteration that Sec. 5.2 reports as the measured rate).  The
