@@ -129,3 +129,20 @@ def test_long_hss_loop_graphs_equal_eager(mixed_form, n, levels, k, steps):
         outs.append(to_host(s.precondition(to_dev(v))))
         s.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_mixed_columns_batch_equals_single_solves():
+    """Mixed columns share every launch but not their arithmetic: a batch of
+    three (one of them zero) equals the single-column solves."""
+    import torch
+    n, k, dh, levels = 32, 8.0, 2.0, 2
+    s = _gpu(n, levels, k, dh, mg_cycles=2)
+    f = np.stack([W.gaussian_nodal(2, n, c, 0.08) for c in ((0.3, 0.4), (0.6, 0.7))])
+    F = s.load_nodal(torch.from_numpy(np.stack([f[0], np.zeros_like(f[0]), f[1]])).cuda())
+    xb, st = s.solve(F, tol=1e-10)
+    xb = to_host(xb)
+    assert st["converged"] == 1
+    assert np.abs(xb[1]).max() == 0.0
+    for c in (0, 2):
+        x1, _ = s.solve(F[c:c + 1].contiguous(), tol=1e-10)
+        assert rel_l2(to_host(x1)[0], xb[c]) < 1e-12

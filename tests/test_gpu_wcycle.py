@@ -85,3 +85,15 @@ def test_w_variant_has_no_coarse_solve():
     s = _gpu(2, 16, 2, 3.0, 3.0, restart=4)
     with pytest.raises(HelmError):
         s.coarse_solve(to_dev(W.random_complex(81, 44)))
+
+
+def test_w_variant_with_richardson_matches_oracle():
+    k, n, levels = 16.0, 64, 4
+    pr = osolver.Problem(2, n, k, 2.0, levels=levels, cycles=1, cycle="w")
+    r0 = pr.M @ W.uniform_source(2, n) - pr.B0 @ W.paper_initial_guess(pr.B0.shape[0], 3)
+    xo, info = pr.solve(r0, tol=1e-6, inner="mg", method="richardson", maxiter=200)
+    x, st = _gpu(2, n, levels, k, 2.0, outer="richardson").solve(to_dev(r0[None]), tol=1e-6)
+    assert st["converged"] == 1
+    assert abs(st["outer_its"] - info["its"]) <= 1, (st["outer_its"], info["its"])
+    if st["outer_its"] == info["its"]:
+        assert rel_l2(to_host(x)[0], xo) < 1e-8
