@@ -82,6 +82,14 @@ def test_create_rejects_bad_options_and_unsupported():
     L.helm_opts_default(ctypes.byref(o))
     o.cycle, o.precision = helm.HELM_CYCLE_W_GMRES, helm.HELM_FP32_MG
     assert _create(helm, L, opts=o)[0] == helm.HELM_ENOTSUP
+    # the mixed element: 2D only, FP64, V cycles
+    assert _create(helm, L, dim=3, elem=helm.HELM_MIXED_DG0_P1)[0] == helm.HELM_EINVAL
+    L.helm_opts_default(ctypes.byref(o))
+    o.precision = helm.HELM_FP32_MG
+    assert _create(helm, L, elem=helm.HELM_MIXED_DG0_P1, opts=o)[0] == helm.HELM_ENOTSUP
+    L.helm_opts_default(ctypes.byref(o))
+    o.cycle = helm.HELM_CYCLE_W_GMRES
+    assert _create(helm, L, elem=helm.HELM_MIXED_DG0_P1, opts=o)[0] == helm.HELM_ENOTSUP
     L.helm_opts_default(ctypes.byref(o))
     o.nu1 = 3
     assert _create(helm, L, opts=o)[0] == helm.HELM_ENOTSUP
@@ -93,6 +101,7 @@ def test_null_handle_calls_are_rejected():
     helm, L = _lib()
     assert L.helm_destroy(None) == helm.HELM_OK
     assert L.helm_nodes(None, 0) == -1
+    assert L.helm_vector_length(None) == -1
     b = ctypes.c_size_t()
     assert L.helm_workspace_bytes(None, 1, ctypes.byref(b)) == helm.HELM_EINVAL
     assert L.helm_solve(None, None, None, 1, 1e-8, None, None) == helm.HELM_EINVAL
