@@ -172,8 +172,10 @@ typedef struct {
     int    full_reorth; /* 1: classical Gram-Schmidt twice at every Arnoldi
                           step; by default the second pass runs only for
                           the columns whose first pass kept less than
-                          1/sqrt(2) of the new vector's norm (Kahan's
-                          criterion; estimated as |w|^2 - |h|^2 on the
+                          1/sqrt(50) ~ 0.14 of the new vector's norm (the
+                          Kahan-Parlett test: one pass leaves an
+                          orthogonality error of ~eps times the inverse of
+                          that fraction; estimated as |w|^2 - |h|^2 on the
                           device, no host synchronisation)                  */
     int    split;      /* 1: with two or more columns, split them into two
                           groups whose HSS loops run on two streams (one

@@ -240,8 +240,8 @@ struct Engine {
             const Vec<cxd> W{Vb(), N, 0, dm + 4 * cap};
             const int nblk = multidot_blocks(N);
             // classical Gram-Schmidt; the second pass runs for the columns
-            // whose first pass cancelled more than 1/sqrt(2) of w's norm
-            // (every column with full_reorth), decided on the device
+            // whose first pass kept less than ~0.14 of w's norm (every
+            // column with full_reorth), decided on the device
             const bool sel = !h->opts.full_reorth;
             const int* flag2 = sel ? d_flag() : nullptr;
             for (int pass = 0; pass < 2; ++pass) {

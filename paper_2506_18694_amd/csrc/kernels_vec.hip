@@ -160,9 +160,12 @@ __global__ __launch_bounds__(BS) void k_multidot(long long N, int m, const int* 
 }
 
 // Second classical Gram-Schmidt pass needed?  With h = V^H w from the first
-// pass and V orthonormal, |w - V h|^2 = |w|^2 - |h|^2; the pass is repeated
-// when that is below |w|^2 / 2 (the first pass cancelled more than a factor
-// 1/sqrt(2) of w's norm), and also when the sums are not finite.
+// pass and V orthonormal, |w - V h|^2 = |w|^2 - |h|^2.  One pass leaves w'
+// orthogonal to V up to about eps |w| / |w'| (the "twice is enough"
+// argument of Kahan and Parlett), so the pass is repeated when |w'| < eta |w|
+// with eta^2 = REORTH_ETA2 (eta ~ 1/7: at most ~7 eps after one pass), and
+// also when the sums are not finite.
+constexpr double REORTH_ETA2 = 0.02;
 __global__ __launch_bounds__(BS) void k_reorth_flag(int m, const int* mlen, int nblk,
                                                     const double* wpart, const cxd* h, int hstride,
                                                     int* flag) {
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(BS) void k_reorth_flag(int m, const int* mlen, int 
         acc[1] += v.x * v.x + v.y * v.y;
     }
     block_sum<2>(acc, lds);
-    if (threadIdx.x == 0) flag[slot] = (acc[1] <= 0.5 * acc[0]) ? 0 : 1;
+    if (threadIdx.x == 0) flag[slot] = (acc[1] <= (1.0 - REORTH_ETA2) * acc[0]) ? 0 : 1;
 }
 
 // one block per (slot, i): out = sum over blocks, fixed order; with flag,
