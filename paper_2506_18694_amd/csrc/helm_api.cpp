@@ -213,9 +213,11 @@ struct helm_s {
     // the loop is captured as a head graph (step 0 and the remainder steps)
     // and a body graph of `block` steps replayed `reps` times, so that no
     // graph holds more than ~20000 launches
+    // (keyed by the workspace address and the column count its layout was
+    // made for: a new workspace of another size can reuse an old address)
     struct GraphEntry {
         void* ws;
-        int s0, ns, tag, cycles;
+        int cap, s0, ns, tag, cycles;
         hipGraphExec_t head, body;
         int reps;
     };
@@ -293,10 +295,12 @@ struct Layout {
     size_t gk[32], ghu, ghu2, gn, gy, gpart, gnpart;
     size_t mg;  // mixed: the per-step triangle data g of every slot
     size_t total;
+    int cap;    // columns the layout was made for (its offsets depend on it)
 };
 
 Layout layout(const helm_t* h, int nrhs) {
     Layout L{};
+    L.cap = nrhs;
     size_t off = 0;
     const size_t smg = h->prec == HELM_FP64 ? sizeof(cxd) : sizeof(cxf);
     auto take = [&](size_t bytes) {
@@ -306,7 +310,9 @@ Layout layout(const helm_t* h, int nrhs) {
     };
     const int R = h->restart;
     const long long N = h->Nl[0];
-    const int nblk = multidot_blocks(N);
+    // reductions run over whole columns (h->nv values: the mixed element's
+    // triangle data included), so their partials are sized for that length
+    const int nblk = multidot_blocks(h->nv);
     L.cols = take(sizeof(int) * nrhs);
     L.maps = take(sizeof(int) * NMAPS * nrhs);
     L.flag = take(sizeof(int) * nrhs);
@@ -921,8 +927,8 @@ void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<c
             const int s0 = q == 0 ? 0 : n0;
             const helm_s::GraphEntry* ge = nullptr;
             for (const auto& e : h->graphs)
-                if (e.ws == ws && e.s0 == s0 && e.ns == grp[q].ns && e.tag == tag &&
-                    e.cycles == h->cycles)
+                if (e.ws == ws && e.cap == Lw.cap && e.s0 == s0 && e.ns == grp[q].ns &&
+                    e.tag == tag && e.cycles == h->cycles)
                     ge = &e;
             if (!ge) {
                 // run the first two steps eagerly before capturing, so that
@@ -956,7 +962,7 @@ void precondition(helm_t* h, const Layout& Lw, void* ws, Vec<const cxd> v, Vec<c
                         reps = (S - 1 - r) / block;
                     }
                 }
-                helm_s::GraphEntry ne{ws, s0, grp[q].ns, tag, h->cycles, nullptr, nullptr, reps};
+                helm_s::GraphEntry ne{ws, Lw.cap, s0, grp[q].ns, tag, h->cycles, nullptr, nullptr, reps};
                 ne.head = instantiate_steps<T>(h, ws, grp[q], 0, head);
                 if (reps > 0) {
                     try {

@@ -154,3 +154,22 @@ def test_no_convergence_reports_enoconv():
     assert st["outer_its"] == 3
     r = np.linalg.norm(b[0] - pr.B0 @ to_host(x)[0]) / np.linalg.norm(b[0])
     assert abs(r - st["true_rel_residual"]) < 1e-10
+
+
+def test_workspaces_of_different_sizes_on_one_handle():
+    """Solves with 3, 2 and 1 columns on one handle get workspaces of
+    different layouts (the binding frees the old one, so a new one can reuse
+    its address); the captured preconditioner graphs must follow the layout:
+    every solve equals the single-column solves."""
+    n, k, levels = 64, 10.0, 3
+    centres = ((0.3, 0.4), (0.6, 0.7), (0.5, 0.2))
+    pr = osolver.Problem(2, n, k, k, levels=levels)
+    b = np.stack([pr.M @ W.gaussian_nodal(2, n, c, 0.05 + 0.02 * i) for i, c in enumerate(centres)])
+    s = _solver(2, n, levels, k, mg_cycles=2)
+    singles = [to_host(s.solve(to_dev(b[c:c + 1]), tol=1e-10)[0])[0] for c in range(3)]
+    for cols in ([0, 1, 2], [2, 0], [1], [0, 1, 2]):
+        x, st = s.solve(to_dev(b[cols]), tol=1e-10)
+        x = to_host(x)
+        assert st["converged"] == 1
+        for q, c in enumerate(cols):
+            assert rel_l2(x[q], singles[c]) < 1e-12, (cols, c)
