@@ -256,7 +256,7 @@ const char* helm_last_error(void);
  * unknown outer or cycle, smooth_its outside 0..20, or (V cycles) a
  * coarsest mesh with more than 4096 nodes; HELM_ENOTSUP for Dirichlet
  * faces, (nu1, nu2) != (2, 2) with V cycles, or the W variant with
- * HELM_FP32_MG; HELM_ENOMEM; HELM_EDEVICE.
+ * HELM_FP32_MG or with the mixed element; HELM_ENOMEM; HELM_EDEVICE.
  * On error *out is set to NULL and nothing is leaked.
  */
 int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,

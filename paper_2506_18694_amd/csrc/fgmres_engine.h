@@ -145,7 +145,7 @@ struct Engine {
 
     void apply_B(int mode, Vec<const cxd> X, Vec<const cxd> Bv, Vec<cxd> Y, int ns) {
         if (h->mixed) {
-            mixed_system(h, h->delta, mode, X, Bv, Y, ns);
+            mixed_system<double>(h, h->delta, mode, X, Bv, Y, ns);
             return;
         }
         const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
@@ -156,11 +156,9 @@ struct Engine {
                                       !h->opts.no_stream);
     }
     void apply_BZ(Vec<const cx<T>> Zv, Vec<cxd> Y, int ns) {
-        if constexpr (std::is_same<T, double>::value) {
-            if (h->mixed) {
-                mixed_system(h, h->delta, MODE_APPLY, Zv, Vec<const cxd>{}, Y, ns);
-                return;
-            }
+        if (h->mixed) {
+            mixed_system<T>(h, h->delta, MODE_APPLY, Zv, Vec<const cxd>{}, Y, ns);
+            return;
         }
         const Coef b0 = h->coef(h->delta == 0.0 ? HELM_OP_B0 : HELM_OP_BDELTA);
         if (h->dim == 2)

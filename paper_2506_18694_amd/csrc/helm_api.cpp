@@ -705,15 +705,17 @@ inline bool w_variant(const helm_t* h) { return h->opts.cycle == HELM_CYCLE_W_GM
 
 // Y = A_delta X (MODE_APPLY) or Y = B - A_delta X (MODE_RESID) for mixed
 // vectors [u | sigma]: u rows (delta - ik) M u + M_Gamma u + G^T sigma,
-// sigma rows (delta - ik) M_s sigma - G u.
-void mixed_system(helm_t* h, double delta, int mode, Vec<const cxd> X, Vec<const cxd> B, Vec<cxd> Y,
-                  int ns) {
+// sigma rows (delta - ik) M_s sigma - G u.  FP64 arithmetic; X in FP64 or
+// in the preconditioner's FP32 storage.
+template <typename TI>
+void mixed_system(helm_t* h, double delta, int mode, Vec<const cx<TI>> X, Vec<const cxd> B,
+                  Vec<cxd> Y, int ns) {
     const zd s(delta, -h->k);
     const double sg = mode == MODE_RESID ? -1.0 : 1.0;
     const Op2<double> op = make_op2<double>(Coef{0.0, sg * s, sg}, h->n, h->omega);
-    mixed_nodes(h->stream, op, mk(1.0, 0.0), mk(sg, 0.0), mk(0.0, 0.0), X,
-                mode == MODE_RESID ? B : Vec<const cxd>{}, Vec<const cxd>{}, Y, ns);
-    mixed_tris(h->stream, h->n, mode, mk(s.real(), s.imag()), X, B, Y, ns);
+    mixed_nodes<double, TI>(h->stream, op, mk(1.0, 0.0), mk(sg, 0.0), mk(0.0, 0.0), X,
+                            mode == MODE_RESID ? B : Vec<const cxd>{}, Vec<const cxd>{}, Y, ns);
+    mixed_tris<double, TI>(h->stream, h->n, mode, mk(s.real(), s.imag()), X, B, Y, ns);
 }
 
 // One HSS step of the mixed shifted-HSS preconditioner with sigma
@@ -722,40 +724,40 @@ void mixed_system(helm_t* h, double delta, int mode, Vec<const cxd> X, Vec<const
 // rho = k(dh-i) [nu (k(dh+i) M u - G^T sigma + k M_Gamma u) + c R_u]
 //       - G^T g - Lmix u,
 // e = q V-cycles on Lmix e = rho, u += e, sigma = (grad u + g) / (k(dh-i)).
+template <typename T>
 void hss_step_mixed(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const long long N = h->Nl[0], Nv = h->nv;
     const double k = h->k;
-    Vec<cxd> U = at_ws<cxd>(ws, Lw.u, Nv);
-    Vec<cxd> R = at_ws<cxd>(ws, Lw.R, Nv);
-    Vec<cxd> G = at_ws<cxd>(ws, Lw.mg, Nv - N);
-    Vec<cxd> rho = at_ws<cxd>(ws, Lw.mg_b[0], N);
-    Vec<cxd> e = at_ws<cxd>(ws, Lw.mg_x[0], N);
-    Vec<cxd> t = at_ws<cxd>(ws, Lw.mg_t[0], N);
+    Vec<cx<T>> U = at_ws<cx<T>>(ws, Lw.u, Nv);
+    Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, Nv);
+    Vec<cx<T>> G = at_ws<cx<T>>(ws, Lw.mg, Nv - N);
+    Vec<cx<T>> rho = at_ws<cx<T>>(ws, Lw.mg_b[0], N);
+    Vec<cx<T>> e = at_ws<cx<T>>(ws, Lw.mg_x[0], N);
+    Vec<cx<T>> t = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
     const double nu = (k - 1.0) / (k + 1.0), c = 2.0 * k / (k + 1.0);
     const zd kp = k * zd(h->dh, 1.0), km = k * zd(h->dh, -1.0);
-    if (s == 0) zero<double>(h->stream, U.base, Nv * ns);
-    mixed_g(h->stream, h->n, mk((nu * kp).real(), (nu * kp).imag()), nu, c, cst(U), cst(R), G, ns);
+    if (s == 0) zero<T>(h->stream, U.base, Nv * ns);
+    mixed_g<T>(h->stream, h->n, tocx<T>(nu * kp), (T)nu, (T)c, cst(U), cst(R), G, ns);
     // k(dh-i) nu (k(dh+i) M + k M_Gamma) - Lmix as one stencil
     const Coef lm = h->coef(HELM_OP_L);
     const Coef comb{-lm.a, km * nu * kp - lm.b, km * nu * k - lm.c};
     const zd sa = -km * nu, sb = km * c;
-    mixed_nodes(h->stream, make_op2<double>(comb, h->n, h->omega), mk(sb.real(), sb.imag()),
-                mk(sa.real(), sa.imag()), mk(-1.0, 0.0), cst(U), cst(R), cst(G), rho, ns);
-    vcycle<double>(h, Lw, ws, 0, cst(rho), e, t, ns);
-    for (int q = 1; q < h->cycles; ++q) vcycle<double>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
-    axpy1<double>(h->stream, N, 1.0, cst(e), U, ns);
-    const zd inv = 1.0 / km;
-    mixed_sigma(h->stream, h->n, mk(inv.real(), inv.imag()), cst(U), cst(G), U, ns);
+    mixed_nodes<T, T>(h->stream, make_op2<T>(comb, h->n, h->omega), tocx<T>(sb), tocx<T>(sa),
+                      mk((T)-1, (T)0), cst(U), cst(R), cst(G), rho, ns);
+    vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns);
+    for (int q = 1; q < h->cycles; ++q) vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
+    axpy1<T>(h->stream, N, (T)1, cst(e), U, ns);
+    mixed_sigma<T>(h->stream, h->n, tocx<T>(1.0 / km), cst(U), cst(G), U, ns);
 }
 
 // HSS step s of the handle's variant on the slot range described by L.
 template <typename T>
 void hss_step(helm_t* h, const Layout& L, void* ws, int ns, int s) {
+    if (h->mixed) {
+        hss_step_mixed<T>(h, L, ws, ns, s);
+        return;
+    }
     if constexpr (std::is_same<T, double>::value) {
-        if (h->mixed) {
-            hss_step_mixed(h, L, ws, ns, s);
-            return;
-        }
         if (w_variant(h)) {
             hss_step_w(h, L, ws, ns, s);
             return;
@@ -1161,7 +1163,7 @@ int richardson_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, 
         const Vec<const cxd> Xr{x, N, 0, d_cols}, Br{rhs, N, 0, d_cols};
         const Vec<cxd> Rr{r, N, 0, nullptr};
         if (h->mixed)
-            mixed_system(h, h->delta, MODE_RESID, Xr, Br, Rr, nr);
+            mixed_system<double>(h, h->delta, MODE_RESID, Xr, Br, Rr, nr);
         else if (h->dim == 2)
             stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), MODE_RESID, 1.0, Xr,
                                       Br, Rr, nr);
@@ -1279,10 +1281,9 @@ void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>>
     SlotGroup g{Lw, ns, s};
     for (int step = 0; step < S; ++step) {
         hss_step<T>(h, g.L, ws, ns, step);
-        if (h->mixed) {
-            if constexpr (std::is_same<T, double>::value)
-                mixed_system(h, h->dh, MODE_RESID, u, vv, rv, ns);
-        } else if (h->dim == 2)
+        if (h->mixed)
+            mixed_system<T>(h, h->dh, MODE_RESID, u, vv, rv, ns);
+        else if (h->dim == 2)
             stencil2d<double, T>(s, make_op2<double>(cb, h->n, h->omega), MODE_RESID, 1.0, u, vv, rv,
                                  ns);
         else
@@ -1381,8 +1382,8 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
     if (bc && bc->dirichlet_faces != 0) return HELM_ENOTSUP;
     if (!wvar && (o.nu1 != 2 || o.nu2 != 2)) return HELM_ENOTSUP;
     if (wvar && o.precision != HELM_FP64) return HELM_ENOTSUP;
-    // the mixed formulation: FP64, V cycles
-    if (mixed && (o.precision != HELM_FP64 || wvar)) return HELM_ENOTSUP;
+    // the mixed formulation: V cycles
+    if (mixed && wvar) return HELM_ENOTSUP;
     const int nc_side = mesh->n >> (mesh->levels - 1);
     long long ncoarse = 1;
     for (int d = 0; d < mesh->dim; ++d) ncoarse *= (nc_side + 1);
@@ -1588,7 +1589,7 @@ int helm_apply(helm_t* h, int op, int level, int prec, const void* x, void* y, i
         if (!h->mixed || level != 0 || prec != HELM_FP64) return HELM_EINVAL;
         const long long Nv = h->nv;
         try {
-            mixed_system(h, op == HELM_OP_MIXED ? h->delta : h->dh, MODE_APPLY,
+            mixed_system<double>(h, op == HELM_OP_MIXED ? h->delta : h->dh, MODE_APPLY,
                          Vec<const cxd>{static_cast<const cxd*>(x), Nv, 0, nullptr}, Vec<const cxd>{},
                          Vec<cxd>{static_cast<cxd*>(y), Nv, 0, nullptr}, nrhs);
             HIPCHK(hipGetLastError());

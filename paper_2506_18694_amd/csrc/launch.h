@@ -111,17 +111,22 @@ void prolong3d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslo
 // X, B, Y of mixed vectors [u | sigma] (sigma after the N = (n+1)^2 nodes).
 // y = sb B_u + Op u + G^T (sa sigma + sg g) at the nodes (B, G nullable; G
 // holds 4 n^2 triangle values per slot); Y addresses node vectors.
-void mixed_nodes(hipStream_t st, const Op2<double>& op, cxd sb, cxd sa, cxd sg, Vec<const cxd> X,
-                 Vec<const cxd> B, Vec<const cxd> G, Vec<cxd> Y, int nslots);
-// sigma rows: y = area (s sigma - grad u)  or  B - area (s sigma - grad u)
-void mixed_tris(hipStream_t st, int n, int mode, cxd s, Vec<const cxd> X, Vec<const cxd> B,
-                Vec<cxd> Y, int nslots);
-// g = nukp sigma + nu grad u + c R_sigma / area
-void mixed_g(hipStream_t st, int n, cxd nukp, double nu, double c, Vec<const cxd> X,
-             Vec<const cxd> R, Vec<cxd> G, int nslots);
-// sigma = inv (grad u + g)
-void mixed_sigma(hipStream_t st, int n, cxd inv, Vec<const cxd> X, Vec<const cxd> G, Vec<cxd> Y,
+template <typename T, typename TI>
+void mixed_nodes(hipStream_t st, const Op2<T>& op, cx<T> sb, cx<T> sa, cx<T> sg,
+                 Vec<const cx<TI>> X, Vec<const cx<T>> B, Vec<const cx<T>> G, Vec<cx<T>> Y,
                  int nslots);
+// sigma rows: y = area (s sigma - grad u)  or  B - area (s sigma - grad u)
+template <typename T, typename TI>
+void mixed_tris(hipStream_t st, int n, int mode, cx<T> s, Vec<const cx<TI>> X, Vec<const cx<T>> B,
+                Vec<cx<T>> Y, int nslots);
+// g = nukp sigma + nu grad u + c R_sigma / area
+template <typename T>
+void mixed_g(hipStream_t st, int n, cx<T> nukp, T nu, T c, Vec<const cx<T>> X, Vec<const cx<T>> R,
+             Vec<cx<T>> G, int nslots);
+// sigma = inv (grad u + g)
+template <typename T>
+void mixed_sigma(hipStream_t st, int n, cx<T> inv, Vec<const cx<T>> X, Vec<const cx<T>> G,
+                 Vec<cx<T>> Y, int nslots);
 
 // ---- vector kernels (kernels_vec.hip) ----------------------------------------
 // x = Ainv b on the coarsest mesh, Ainv dense complex FP64 (nc x nc, row-major)

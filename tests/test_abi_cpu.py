@@ -82,11 +82,8 @@ def test_create_rejects_bad_options_and_unsupported():
     L.helm_opts_default(ctypes.byref(o))
     o.cycle, o.precision = helm.HELM_CYCLE_W_GMRES, helm.HELM_FP32_MG
     assert _create(helm, L, opts=o)[0] == helm.HELM_ENOTSUP
-    # the mixed element: 2D only, FP64, V cycles
+    # the mixed element: 2D only, V cycles
     assert _create(helm, L, dim=3, elem=helm.HELM_MIXED_DG0_P1)[0] == helm.HELM_EINVAL
-    L.helm_opts_default(ctypes.byref(o))
-    o.precision = helm.HELM_FP32_MG
-    assert _create(helm, L, elem=helm.HELM_MIXED_DG0_P1, opts=o)[0] == helm.HELM_ENOTSUP
     L.helm_opts_default(ctypes.byref(o))
     o.cycle = helm.HELM_CYCLE_W_GMRES
     assert _create(helm, L, elem=helm.HELM_MIXED_DG0_P1, opts=o)[0] == helm.HELM_ENOTSUP

@@ -44,16 +44,17 @@ def test_mixed_operator_and_rhs_match_oracle(n):
     assert rel_l2(b, mp.rhs(mp.M @ f)) < 1e-13
 
 
-@pytest.mark.parametrize("levels,cycles", [(1, 1), (3, 2)])
-def test_mixed_preconditioner_matches_oracle(levels, cycles):
+@pytest.mark.parametrize("levels,cycles,prec,tol", [(1, 1, "fp64", 1e-11), (3, 2, "fp64", 1e-11),
+                                                   (3, 2, "fp32", 2e-4)])
+def test_mixed_preconditioner_matches_oracle(levels, cycles, prec, tol):
     n, k, dh = 32, 8.0, 2.0
     mp = mixed.MixedProblem(n, k, dh)
     solve = _lmix_solver(mp, levels, cycles)
     R = W.random_complex((2, mp.N + mp.E2), 52)
-    s = _gpu(n, levels, k, dh, restart=4, mg_cycles=cycles)
+    s = _gpu(n, levels, k, dh, restart=4, mg_cycles=cycles, precision=prec)
     z = to_host(s.precondition(to_dev(R)))
     ref = np.stack([mp.precond(r, solve_lmix=solve) for r in R])
-    assert rel_l2(z, ref) < 1e-11
+    assert rel_l2(z, ref) < tol
 
 
 def test_mixed_hss_history_matches_oracle():
@@ -72,8 +73,9 @@ def test_mixed_hss_history_matches_oracle():
     assert rel_l2(to_host(z)[0], U) < 1e-11
 
 
-@pytest.mark.parametrize("outer", ["fgmres", "richardson"])
-def test_mixed_solve_gives_the_primal_solution(outer):
+@pytest.mark.parametrize("outer,prec", [("fgmres", "fp64"), ("richardson", "fp64"),
+                                        ("fgmres", "fp32")])
+def test_mixed_solve_gives_the_primal_solution(outer, prec):
     import torch
     n, k, dh, levels = 64, 16.0, 2.0, 3
     mp = mixed.MixedProblem(n, k, dh)
@@ -86,12 +88,13 @@ def test_mixed_solve_gives_the_primal_solution(outer):
         _, info = krylov.fgmres(A, F, P, tol=1e-10, restart=100, maxiter=100)
     else:
         _, info = krylov.richardson(A, F, P, tol=1e-10, maxiter=200)
-    s = _gpu(n, levels, k, dh, mg_cycles=2, outer=outer)
+    s = _gpu(n, levels, k, dh, mg_cycles=2, outer=outer, precision=prec)
     Fd = s.load_nodal(torch.from_numpy(f[None]).cuda())
     x, st = s.solve(Fd, tol=1e-10)
     x = to_host(x)[0]
     assert st["converged"] == 1
-    assert abs(st["outer_its"] - info["its"]) <= 1, (st["outer_its"], info["its"])
+    slack = 1 if prec == "fp64" else 2
+    assert abs(st["outer_its"] - info["its"]) <= slack, (st["outer_its"], info["its"])
     assert np.linalg.norm(F - mp.A0 @ x) <= 1e-10 * 1.01 * np.linalg.norm(F)
     u = osolver.Problem(2, n, k, dh).solve_direct(mp.M @ f)
     assert rel_l2(x[:mp.N], u) < 1e-6
