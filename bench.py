@@ -307,7 +307,9 @@ def main():
                     help="run the continuous-batching serving workload instead (one JSON line)")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--sizes", default="128,256,512")
-    ap.add_argument("--rate", type=float, default=8.0)
+    ap.add_argument("--rate", default="auto",
+                    help="Poisson arrival rate (requests/s), or 'auto': 0.8 of the capacity "
+                         "measured by a saturating batch of requests first")
     ap.add_argument("--max-cols", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=120.0)
     ap.add_argument("--paper", action="store_true",
@@ -353,14 +355,28 @@ def main():
         return
     if args.serving:
         sizes = tuple(int(v) for v in args.sizes.split(","))
-        res = run_serving(W, args.requests, sizes, args.rate, args.max_cols, args.budget_gb, "fp32")
+        capacity = None
+        if args.rate == "auto":
+            # capacity: a batch of requests all queued at t = 0 (another seed)
+            probe = run_serving(W, max(16, args.requests // 4), sizes, None, args.max_cols,
+                                args.budget_gb, "fp32", seed=2)
+            capacity = probe["requests"] / probe["makespan_s"]
+            rate = 0.8 * capacity
+            log("[serving] capacity %.2f requests/s; offered load 0.8 -> %.2f requests/s"
+                % (capacity, rate))
+        else:
+            rate = float(args.rate)
+        res = run_serving(W, args.requests, sizes, rate, args.max_cols, args.budget_gb, "fp32")
+        res["capacity_req_per_s"] = capacity
+        res["offered_load"] = rate / capacity if capacity else None
         out = {"metric": "serving p50/p99 latency (continuous batching, FP32-MG/FP64-outer)",
                "value": res["p99_latency_s"], "unit": "s (p99)", "n_gpus": 1, "steps": 1,
                "warmup": 0, "ms_per_step": res["makespan_s"] * 1e3, "higher_is_better": False,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
                "config": {"workload": "serving-2d-p1", **{k: v for k, v in res.items()
                                                           if k in ("requests", "sizes", "rate_per_s",
-                                                                   "max_cols", "precision")}},
+                                                                   "max_cols", "precision",
+                                                                   "offered_load")}},
                "serving": res}
         print(json.dumps(out), flush=True)
         return
