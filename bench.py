@@ -211,6 +211,57 @@ PAPER_MG_MIXED = {16.0: {"fgmres": {0.5: 38, 1.0: 9, 1.5: 7}, "eta_s": 0.8806, "
                   128.0: {"fgmres": {0.5: 85, 1.0: 7, 1.5: 3}, "eta_s": 0.9842, "eta_h": 0.1796}}
 
 
+# The paper's weak-scaling convergence tables (box source, FGMRES runs):
+# measured HSS rate eta_s, its bound nu_s and the multigrid rate eta_mg of
+# its W-cycle, for 2D k = 64..512 and 3D k = 20, 40, 80.
+PAPER_WEAK = {(2, 64.0): (0.9677, 0.00336), (2, 128.0): (0.9837, 0.00199),
+              (2, 256.0): (0.9920, 0.00109), (2, 512.0): (0.9960, 0.00072),
+              (3, 20.0): (0.9029, 0.01931), (3, 40.0): (0.9492, 0.01507),
+              (3, 80.0): (0.9748, 0.00950)}
+
+
+def run_paper_rates(W, dims=(2, 3), seed=3):
+    """The HSS and multigrid rates of the paper's weak-scaling runs on one
+    GPU (delta_hat = 2, box source, ceil(k) HSS steps with the library's
+    V(2,2) cycles): eta_s from the per-step HSS residuals of one
+    preconditioner application to the random guess's residual, eta_mg as
+    the residual contraction of one cycle on a random right-hand side."""
+    import torch
+    from paper_2506_18694_amd import Solver
+    rows = []
+    for dim in dims:
+        meshes = W.WEAK_MESHES_2D if dim == 2 else W.WEAK_MESHES_3D
+        for k, (n, levels) in meshes.items():
+            t0 = time.perf_counter()
+            s = Solver(dim, n, levels, k, 0.0, 2.0, restart=1)
+            N = s.N
+            f = torch.from_numpy(W.box_source(n, dim)).to("cuda").reshape(1, N)
+            b = s.load_nodal(f)
+            x0 = torch.from_numpy(W.paper_initial_guess(N, seed)).to("cuda").reshape(1, N)
+            R = (b - s.apply("B0", x0)).contiguous()
+            _, res = s.hss_history(R)
+            steps = res.shape[1] - 1
+            g = torch.Generator(device="cuda").manual_seed(seed)
+            rb = torch.randn(1, N, dtype=torch.complex128, device="cuda", generator=g)
+            rx = s.vcycle(rb)
+            eta_mg = float(torch.linalg.vector_norm(rb - s.apply("L", rx)) /
+                           torch.linalg.vector_norm(rb))
+            torch.cuda.synchronize()
+            p_eta, p_mg = PAPER_WEAK[(dim, k)]
+            row = {"dim": dim, "k": k, "n": n, "levels": levels, "dofs": N,
+                   "eta_s": float((res[0, -1] / res[0, 0]) ** (1.0 / steps)),
+                   "nu_s": (k - 1.0) / (k + 1.0), "paper_eta_s": p_eta,
+                   "eta_mg_vcycle": eta_mg, "paper_eta_mg_wcycle": p_mg,
+                   "s": time.perf_counter() - t0}
+            log("[rates] %dD k=%g n=%d: eta_s %.4f (nu_s %.4f, paper %.4f), one V-cycle %.3f, %.1fs"
+                % (dim, k, n, row["eta_s"], row["nu_s"], p_eta, eta_mg, row["s"]))
+            rows.append(row)
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+    return rows
+
+
 def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "richardson"), seed=3,
               form="primal"):
     """The paper's experiment of Sec. 5.3 on the GPU path: delta_hat = 2,
@@ -316,6 +367,8 @@ def main():
                     help="run the paper's own settings (delta_hat = 2, uniform and box sources, "
                          "theta sweep, FGMRES and Richardson) and print their counts and rates")
     ap.add_argument("--paper-k", default="16,32,64,128")
+    ap.add_argument("--paper-rates", action="store_true",
+                    help="HSS and multigrid rates at the meshes of the paper's weak-scaling runs")
     ap.add_argument("--paper-precision", default="fp64")
     ap.add_argument("--paper-cycle", choices=("v", "w"), default="v",
                     help="v: the library's V(2,2) Jacobi cycles; w: the paper's W-cycle with "
@@ -335,6 +388,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.paper_rates:
+        t0 = time.perf_counter()
+        rows = run_paper_rates(W)
+        out = {"metric": "HSS and multigrid contraction rates at the paper's weak-scaling meshes",
+               "value": None, "unit": "rate", "n_gpus": 1, "steps": 1, "warmup": 0,
+               "ms_per_step": (time.perf_counter() - t0) * 1e3, "higher_is_better": False,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "paper-weak-scaling-meshes-delta_hat2"}, "table": rows}
+        print(json.dumps(out), flush=True)
+        return
     if args.paper:
         ks = [float(v) for v in args.paper_k.split(",")]
         t0 = time.perf_counter()

@@ -83,10 +83,11 @@ def uniform_source(dim, n):
     return np.ones((n + 1) ** dim)
 
 
-def box_source(n):
-    """The paper's box source: 1 on [0.4, 0.6]^2, 0 elsewhere (nodal)."""
-    x, y = node_coordinates(2, n)
-    inside = (x >= 0.4 - 1e-12) & (x <= 0.6 + 1e-12) & (y >= 0.4 - 1e-12) & (y <= 0.6 + 1e-12)
+def box_source(n, dim=2):
+    """The paper's box source: 1 on [0.4, 0.6]^dim, 0 elsewhere (nodal)."""
+    inside = np.ones((n + 1) ** dim, dtype=bool)
+    for x in node_coordinates(dim, n):
+        inside &= (x >= 0.4 - 1e-12) & (x <= 0.6 + 1e-12)
     return inside.astype(np.float64)
 
 
@@ -95,6 +96,13 @@ def box_source(n):
 # divisible by 2^(levels-1) with a coarsest mesh of at most 4096 nodes are
 # rounded up (c0 = 1.00, 1.02, 1.00, 1.02).
 PAPER_MESHES = {16.0: (64, 3), 32.0: (184, 4), 64.0: (512, 5), 128.0: (1472, 7)}
+
+# The meshes of the paper's weak-scaling runs (about 0.5 k^(3/2) cells per
+# side in 2D, 0.54 k^(3/2) in 3D: 257^2 ... and 49^3, 129^3, 361^3 nodes),
+# rounded to sizes the hierarchy divides down to a small coarsest mesh
+# (c0 = 0.50, 0.49, 0.50, 0.49 in 2D): k -> (cells per side, levels).
+WEAK_MESHES_2D = {64.0: (256, 6), 128.0: (704, 7), 256.0: (2048, 9), 512.0: (5632, 10)}
+WEAK_MESHES_3D = {20.0: (48, 3), 40.0: (128, 5), 80.0: (352, 6)}
 
 
 def paper_initial_guess(count, seed):
