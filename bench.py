@@ -213,9 +213,10 @@ PAPER_MG_MIXED = {16.0: {"fgmres": {0.5: 38, 1.0: 9, 1.5: 7}, "eta_s": 0.8806, "
 
 # The paper's weak-scaling convergence tables (box source, FGMRES runs):
 # measured HSS rate eta_s, its bound nu_s and the multigrid rate eta_mg of
-# its W-cycle, for 2D k = 64..512 and 3D k = 20, 40, 80.
+# its W-cycle, for 2D k = 64..1024 and 3D k = 20, 40, 80.
 PAPER_WEAK = {(2, 64.0): (0.9677, 0.00336), (2, 128.0): (0.9837, 0.00199),
               (2, 256.0): (0.9920, 0.00109), (2, 512.0): (0.9960, 0.00072),
+              (2, 1024.0): (0.9980, 0.00057),
               (3, 20.0): (0.9029, 0.01931), (3, 40.0): (0.9492, 0.01507),
               (3, 80.0): (0.9748, 0.00950)}
 

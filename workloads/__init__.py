@@ -101,7 +101,8 @@ PAPER_MESHES = {16.0: (64, 3), 32.0: (184, 4), 64.0: (512, 5), 128.0: (1472, 7)}
 # side in 2D, 0.54 k^(3/2) in 3D: 257^2 ... and 49^3, 129^3, 361^3 nodes),
 # rounded to sizes the hierarchy divides down to a small coarsest mesh
 # (c0 = 0.50, 0.49, 0.50, 0.49 in 2D): k -> (cells per side, levels).
-WEAK_MESHES_2D = {64.0: (256, 6), 128.0: (704, 7), 256.0: (2048, 9), 512.0: (5632, 10)}
+WEAK_MESHES_2D = {64.0: (256, 6), 128.0: (704, 7), 256.0: (2048, 9), 512.0: (5632, 10),
+                  1024.0: (16384, 12)}
 WEAK_MESHES_3D = {20.0: (48, 3), 40.0: (128, 5), 80.0: (352, 6)}
 
 
