@@ -192,3 +192,17 @@ def test_paper_k16_fgmres_rate_from_random_guess(pr):
         assert abs(st["outer_rate"] - 0.2264) < 0.01, st["outer_rate"]
         counts.append(st["outer_its"])
     assert counts[0] == counts[1] and 8 <= counts[0] <= 10, counts
+
+
+def test_richardson_3d_matches_oracle():
+    from paper_2506_18694_amd import Solver
+    n, levels, k = 8, 2, 3.0
+    pr3 = osolver.Problem(3, n, k, 1.0, levels=levels, cycles=2)
+    b = pr3.M @ W.box_source(n, 3)
+    xo, info = pr3.solve(b, tol=1e-8, inner="mg", method="richardson", maxiter=200)
+    x, st = Solver(3, n, levels, k, 0.0, 1.0, mg_cycles=2, outer="richardson").solve(
+        to_dev(b[None]), tol=1e-8)
+    assert st["converged"] == 1
+    assert abs(st["outer_its"] - info["its"]) <= 1, (st["outer_its"], info["its"])
+    if st["outer_its"] == info["its"]:
+        assert rel_l2(to_host(x)[0], xo) < 1e-9

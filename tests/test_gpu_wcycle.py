@@ -97,3 +97,15 @@ def test_w_variant_with_richardson_matches_oracle():
     assert abs(st["outer_its"] - info["its"]) <= 1, (st["outer_its"], info["its"])
     if st["outer_its"] == info["its"]:
         assert rel_l2(to_host(x)[0], xo) < 1e-8
+
+
+def test_w_variant_hss_history_matches_oracle():
+    from oracle import hss
+    k, n, levels = 16.0, 64, 4
+    pr = osolver.Problem(2, n, k, 2.0, levels=levels, cycles=1, cycle="w")
+    R = pr.M @ W.box_source(n) - pr.B0 @ W.paper_initial_guess(pr.B0.shape[0], 3)
+    hist = []
+    hss.hss_correction(pr.Bdh, R, k, 16, pr.mg_solve, hist)
+    ref = np.array([np.linalg.norm(R)] + [np.linalg.norm(R - pr.Bdh @ u) for u in hist])
+    _, res = _gpu(2, n, levels, k, 2.0, restart=4).hss_history(to_dev(R[None]))
+    assert np.abs(res[0] - ref).max() < 1e-10 * ref[0]
