@@ -23,7 +23,9 @@ void mixed_system(helm_t* h, double delta, int mode, Vec<const cx<TI>> X, Vec<co
 // g = nu (k(dh+i) sigma + grad u) + c M_s^{-1} R_sigma (per triangle),
 // rho = k(dh-i) [nu (k(dh+i) M u - G^T sigma + k M_Gamma u) + c R_u]
 //       - G^T g - Lmix u,
-// e = q V-cycles on Lmix e = rho, u += e, sigma = (grad u + g) / (k(dh-i)).
+// e = q V-cycles on Lmix e = rho (the streaming kernels of the primal
+// form, whose operator differs only in its coefficients), u += e,
+// sigma = (grad u + g) / (k(dh-i)).
 template <typename T>
 void hss_step_mixed(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const long long N = h->Nl[0], Nv = h->nv;
@@ -44,8 +46,23 @@ void hss_step_mixed(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const zd sa = -km * nu, sb = km * c;
     mixed_nodes<T, T>(h->stream, make_op2<T>(comb, h->n, h->omega), tocx<T>(sb), tocx<T>(sa),
                       mk((T)-1, (T)0), cst(U), cst(R), cst(G), rho, ns);
-    vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns);
-    for (int q = 1; q < h->cycles; ++q) vcycle<T>(h, Lw, ws, 0, cst(rho), e, t, ns, true);
-    axpy1<T>(h->stream, N, (T)1, cst(e), U, ns);
+    // q cycles x <- x + V(rho - Lmix x) from x = 0, each added into u as it
+    // comes: a zero-guess cycle with the streaming kernels on the current
+    // residual, whose update rho - Lmix d is formed out of place; the
+    // residual, the cycle's result and its scratch rotate through the three
+    // level-0 buffers
+    Vec<cx<T>> buf[3] = {rho, e, t};
+    int ib = 0;  // the buffer holding the current residual
+    for (int q = 0; q < h->cycles; ++q) {
+        const int i1 = (ib + 1) % 3, i2 = (ib + 2) % 3;
+        const Vec<cx<T>> d = vcycle2d_zero<T>(h, Lw, ws, 0, cst(buf[ib]), buf[i1], buf[i2], ns);
+        axpy1<T>(h->stream, N, (T)1, cst(d), U, ns);
+        if (q + 1 < h->cycles) {
+            const int id = d.base == buf[i1].base ? i1 : i2;
+            const int in = 3 - ib - id;
+            apply_mode<T>(h, HELM_OP_L, 0, MODE_RESID, (T)1, cst(d), cst(buf[ib]), buf[in], ns);
+            ib = in;
+        }
+    }
     mixed_sigma<T>(h->stream, h->n, tocx<T>(1.0 / km), cst(U), cst(G), U, ns);
 }
