@@ -127,3 +127,15 @@ def test_server_rejects_invalid_options():
     assert L.helm_server_load(out, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)) == helm.HELM_OK
     assert (q.value, r.value, b.value) == (0, 0, 0.0)
     assert L.helm_server_destroy(out) == helm.HELM_OK
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No CPU fallback: with libhelm.so absent, loading the binding raises
+    and a solver cannot be created."""
+    from paper_2506_18694_amd import helm
+    monkeypatch.setattr(helm, "_lib", None)
+    monkeypatch.setattr(helm, "LIB_PATH", str(tmp_path / "libhelm.so"))
+    with pytest.raises(ImportError):
+        helm.lib()
+    with pytest.raises(ImportError):
+        helm.Solver(2, 8, 2, 2.0, 0.0, 2.0)
