@@ -47,3 +47,56 @@ def rel_err(a, b):
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def q1_b0_rows(n, k, ijk):
+    """Rows of the 3D Q1 operator B_0 = K - k^2 M - i k M_Gamma (every face
+    Sommerfeld) for the nodes ijk = [(i, j, l), ...], built one row at a
+    time from the oracle's element and face matrices, so that a mesh too
+    large to assemble can be checked on sampled nodes.  Returns a list of
+    (columns, values)."""
+    h = 1.0 / n
+    kl, ml = fem.q1_element_matrices(h)
+    gl = fem.q1_face_matrix(h)
+    idx = lambda i, j, l: i + (n + 1) * (j + (n + 1) * l)
+    rows = []
+    for (i, j, l) in ijk:
+        acc = {}
+        c = (i, j, l)
+        for r in (l - 1, l):
+            for q in (j - 1, j):
+                for p in (i - 1, i):
+                    if not (0 <= p < n and 0 <= q < n and 0 <= r < n):
+                        continue
+                    a = (i - p) + 2 * (j - q) + 4 * (l - r)
+                    for b in range(8):
+                        col = idx(p + (b & 1), q + ((b >> 1) & 1), r + ((b >> 2) & 1))
+                        acc[col] = acc.get(col, 0.0) + kl[a, b] - k * k * ml[a, b]
+        # boundary faces: x faces span (y, z), y faces (x, z), z faces (x, y)
+        for ax, (u, v) in ((0, (1, 2)), (1, (0, 2)), (2, (0, 1))):
+            if c[ax] not in (0, n):
+                continue
+            for bv in (c[v] - 1, c[v]):
+                for au in (c[u] - 1, c[u]):
+                    if not (0 <= au < n and 0 <= bv < n):
+                        continue
+                    loc = (c[u] - au) + 2 * (c[v] - bv)
+                    for m in range(4):
+                        node = list(c)
+                        node[u], node[v] = au + (m & 1), bv + (m >> 1)
+                        col = idx(*node)
+                        acc[col] = acc.get(col, 0.0) - 1j * k * gl[loc, m]
+        cols = np.array(sorted(acc), dtype=np.int64)
+        rows.append((cols, np.array([acc[cc] for cc in cols], dtype=np.complex128)))
+    return rows
+
+
+def sample_nodes_3d(n, count, seed):
+    """The 8 corners, one node on every edge and face, and `count` random
+    nodes of the (n+1)^3 grid."""
+    rng = np.random.default_rng(seed)
+    pts = [(i, j, l) for i in (0, n) for j in (0, n) for l in (0, n)]
+    m = n // 2
+    pts += [(m, 0, 0), (0, m, n), (n, n, m), (m, m, 0), (0, m, m), (m, n, m), (n, m, m)]
+    pts += [tuple(int(v) for v in rng.integers(0, n + 1, 3)) for _ in range(count)]
+    return pts

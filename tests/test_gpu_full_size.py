@@ -1,0 +1,120 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (all right-hand sides in one batch on one stream, the
+preconditioner run eagerly with the dominant kernel's launches bracketed
+by events, register-streaming kernels on every level down to the
+LDS-resident small levels).
+
+2D P1 1024 x 1024, k = delta_hat = 100, 8 levels, four right-hand sides:
+every output of the operator apply, of one V-cycle and of two shifted-HSS
+steps is compared with the oracle element by element; the full solve to
+1e-8 is checked through its true residual, recomputed with the oracle's
+assembled B_0 (the direct solve of a million complex unknowns is left to
+the smaller cases).  3D Q1 256^3, k = 40: the operator apply on sampled
+nodes (corners, edges, faces and random interior nodes), the rows built
+from the oracle's element matrices.  Tolerances as in the per-step tests.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import solver as osolver
+import workloads as W
+from gpu_util import q1_b0_rows, rel_err, rel_l2, sample_nodes_3d, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+HEAD = "p1-1024-k100"
+DT = {"fp64": "complex128", "fp32": "complex64"}
+
+
+def _bench_solver(name, prec, **kw):
+    """A solver with the options the benchmark's timed solves use."""
+    from paper_2506_18694_amd import Solver
+    w = W.WORKLOADS[name]
+    return Solver(w["dim"], w["n"], w["levels"], w["k"], w["delta"], w["delta_hat"],
+                  precision=prec, profile=True, streaming=True, split=False, **kw)
+
+
+@pytest.fixture(scope="module")
+def head():
+    w = W.WORKLOADS[HEAD]
+    pr = osolver.Problem(2, w["n"], w["k"], w["delta_hat"], levels=w["levels"], cycles=3)
+    _ = pr.hierarchy
+    return w, pr
+
+
+def _inputs(N, nrhs, seed, prec):
+    x = W.random_complex((nrhs, N), seed)
+    if prec == "fp32":
+        x = x.astype(np.complex64).astype(np.complex128)
+    return x
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_headline_operator_apply(head, prec, tol):
+    w, pr = head
+    s = _bench_solver(HEAD, prec)
+    x = _inputs(s.N, w["nrhs"], 41, prec)
+    for op, A in (("B0", pr.B0), ("L", pr.L)):
+        y = to_host(s.apply(op, to_dev(x, DT[prec])))
+        ref = np.stack([A @ xi for xi in x])
+        assert rel_err(y, ref) < tol, op
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-4)])
+def test_headline_vcycle(head, prec, tol):
+    w, pr = head
+    s = _bench_solver(HEAD, prec, mg_cycles=3)
+    b = _inputs(s.N, w["nrhs"], 43, prec)
+    x = to_host(s.vcycle(to_dev(b, DT[prec])))
+    for xi, bi in zip(x, b):
+        assert rel_l2(xi, pr.vcycle(bi)) < tol
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 5e-4)])
+def test_headline_two_hss_steps(head, prec, tol):
+    """Two HSS steps with three V-cycles each: the step whose residual is
+    c R (u = 0) and one with the residual of a nonzero iterate."""
+    w, pr = head
+    s = _bench_solver(HEAD, prec, mg_cycles=3, hss_steps=2)
+    v = W.random_complex((w["nrhs"], s.N), 45)
+    z = to_host(s.precondition(to_dev(v)))
+    for zi, vi in zip(z, v):
+        assert rel_l2(zi, pr.precond(vi, inner="mg", steps=2)) < tol
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_headline_solve_true_residual(head, prec):
+    import torch
+    w, pr = head
+    s = _bench_solver(HEAD, prec)
+    f = torch.from_numpy(W.workload_sources(HEAD)).cuda().contiguous()
+    b = s.load_nodal(f)
+    x, st = s.solve(b, tol=1e-8)
+    assert st["converged"]
+    bh, xh = to_host(b), to_host(x)
+    for bi, xi in zip(bh, xh):
+        assert np.linalg.norm(bi - pr.B0 @ xi) / np.linalg.norm(bi) <= 1.01e-8
+    # the load vector itself against the oracle's mass matrix
+    fh = W.workload_sources(HEAD)
+    assert rel_err(bh, np.stack([pr.M @ fi for fi in fh])) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_3d_full_size_apply_sampled(prec, tol):
+    name = "q1-256-k40"
+    w = W.WORKLOADS[name]
+    s = _bench_solver(name, prec)
+    n, k = w["n"], w["k"]
+    x = _inputs(s.N, 1, 47, prec)
+    y = to_host(s.apply("B0", to_dev(x, DT[prec])))[0]
+    pts = sample_nodes_3d(n, 400, 48)
+    rows = q1_b0_rows(n, k, pts)
+    ref = np.array([vals @ x[0][cols] for cols, vals in rows])
+    got = np.array([y[i + (n + 1) * (j + (n + 1) * l)] for (i, j, l) in pts])
+    assert rel_err(got, ref) < tol
+    s.close()

@@ -145,3 +145,16 @@ def test_mms_q1_second_order():
     errs = [_mms_error(3, n, 2.0, 0.5, (1.5, 1.0, -0.5)) for n in (4, 8, 16)]
     rates = [errs[i] / errs[i + 1] for i in range(2)]
     assert all(3.4 < r < 4.6 for r in rates), rates
+
+
+def test_sampled_q1_rows_match_assembled_b0():
+    """The row-at-a-time 3D B_0 used to check meshes too large to assemble
+    equals the assembled operator on every row of a small mesh."""
+    from gpu_util import q1_b0_rows, oracle_matrix
+    n, k = 5, 3.5
+    B = oracle_matrix(3, n, "B0", k, k).toarray()
+    allpts = [(i, j, l) for l in range(n + 1) for j in range(n + 1) for i in range(n + 1)]
+    for r, (cols, vals) in enumerate(q1_b0_rows(n, k, allpts)):
+        row = np.zeros(B.shape[1], complex)
+        row[cols] = vals
+        assert np.abs(row - B[r]).max() < 1e-14 * np.abs(B).max()
