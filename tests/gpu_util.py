@@ -100,3 +100,55 @@ def sample_nodes_3d(n, count, seed):
     pts += [(m, 0, 0), (0, m, n), (n, n, m), (m, m, 0), (0, m, m), (m, n, m), (n, m, m)]
     pts += [tuple(int(v) for v in rng.integers(0, n + 1, 3)) for _ in range(count)]
     return pts
+
+
+def p1_b0_rows(n, k, ij):
+    """Rows of the 2D P1 operator B_0 = K - k^2 M - i k M_Gamma (every side
+    Sommerfeld) on the right-diagonal mesh for the nodes ij, one row at a
+    time from the oracle's element matrices (see q1_b0_rows)."""
+    h = 1.0 / n
+    idx = lambda i, j: i + (n + 1) * j
+    rows = []
+    for (i, j) in ij:
+        acc = {}
+        for q in (j - 1, j):
+            for p in (i - 1, i):
+                if not (0 <= p < n and 0 <= q < n):
+                    continue
+                for tri in (((p, q), (p + 1, q), (p + 1, q + 1)),
+                            ((p, q), (p + 1, q + 1), (p, q + 1))):
+                    if (i, j) not in tri:
+                        continue
+                    xy = np.array([[[a * h, b * h] for a, b in tri]])
+                    kl, ml = fem.p1_element_matrices(xy)
+                    a = tri.index((i, j))
+                    for b, (bi, bj) in enumerate(tri):
+                        col = idx(bi, bj)
+                        acc[col] = acc.get(col, 0.0) + kl[0, a, b] - k * k * ml[0, a, b]
+        # boundary edges of length h: (h / 6) [[2, 1], [1, 2]]
+        for ax in (0, 1):
+            c = (i, j)
+            if c[ax] not in (0, n):
+                continue
+            o = 1 - ax
+            for e0 in (c[o] - 1, c[o]):
+                if not 0 <= e0 < n:
+                    continue
+                for e in (e0, e0 + 1):
+                    node = [0, 0]
+                    node[ax], node[o] = c[ax], e
+                    w = (2.0 if e == c[o] else 1.0) * h / 6.0
+                    col = idx(*node)
+                    acc[col] = acc.get(col, 0.0) - 1j * k * w
+        cols = np.array(sorted(acc), dtype=np.int64)
+        rows.append((cols, np.array([acc[cc] for cc in cols], dtype=np.complex128)))
+    return rows
+
+
+def sample_nodes_2d(n, count, seed):
+    """The 4 corners, a node on each side, and `count` random nodes."""
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    pts = [(0, 0), (n, 0), (0, n), (n, n), (m, 0), (0, m), (n, m), (m, n)]
+    pts += [tuple(int(v) for v in rng.integers(0, n + 1, 2)) for _ in range(count)]
+    return pts

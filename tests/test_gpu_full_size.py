@@ -11,7 +11,11 @@ steps is compared with the oracle element by element; the full solve to
 assembled B_0 (the direct solve of a million complex unknowns is left to
 the smaller cases).  3D Q1 256^3, k = 40: the operator apply on sampled
 nodes (corners, edges, faces and random interior nodes), the rows built
-from the oracle's element matrices.  Tolerances as in the per-step tests.
+from the oracle's element matrices.  2D P1 2048 x 2048, k = 200 (too large
+for the oracle's assembly in a test): the B_0 apply on sampled rows, and
+the FP32-multigrid solve through the residual of the library's B_0 apply,
+whose sampled rows are checked against the oracle on the solution itself.
+Tolerances as in the per-step tests.
 """
 
 import numpy as np
@@ -19,7 +23,8 @@ import pytest
 
 from oracle import solver as osolver
 import workloads as W
-from gpu_util import q1_b0_rows, rel_err, rel_l2, sample_nodes_3d, to_dev, to_host
+from gpu_util import (p1_b0_rows, q1_b0_rows, rel_err, rel_l2, sample_nodes_2d, sample_nodes_3d,
+                      to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -118,3 +123,43 @@ def test_3d_full_size_apply_sampled(prec, tol):
     got = np.array([y[i + (n + 1) * (j + (n + 1) * l)] for (i, j, l) in pts])
     assert rel_err(got, ref) < tol
     s.close()
+
+
+def _sampled_2d(n, k, v, y, seed):
+    pts = sample_nodes_2d(n, 400, seed)
+    rows = p1_b0_rows(n, k, pts)
+    ref = np.array([vals @ v[cols] for cols, vals in rows])
+    got = np.array([y[i + (n + 1) * j] for (i, j) in pts])
+    return rel_err(got, ref)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_2048_apply_sampled(prec, tol):
+    name = "p1-2048-k200"
+    w = W.WORKLOADS[name]
+    s = _bench_solver(name, prec)
+    x = _inputs(s.N, 1, 49, prec)
+    y = to_host(s.apply("B0", to_dev(x, DT[prec])))[0]
+    assert _sampled_2d(w["n"], w["k"], x[0], y, 50) < tol
+    s.close()
+
+
+def test_2048_fp32_solve_residual():
+    import torch
+    name = "p1-2048-k200"
+    w = W.WORKLOADS[name]
+    s = _bench_solver(name, "fp32")
+    f = torch.from_numpy(W.workload_sources(name)).cuda().contiguous()
+    b = s.load_nodal(f)
+    x, st = s.solve(b, tol=1e-8)
+    assert st["converged"]
+    # the residual through the FP64 apply of an FP64 handle on the same mesh
+    s64 = _bench_solver(name, "fp64")
+    y = to_host(s64.apply("B0", x))[0]
+    bh, xh = to_host(b)[0], to_host(x)[0]
+    assert np.linalg.norm(bh - y) / np.linalg.norm(bh) <= 1.01e-8
+    # B_0 x ~ b is about 1e3 times smaller than sum |w_ij x_j| here, so the
+    # summation-order difference is relatively larger than on random input
+    assert _sampled_2d(w["n"], w["k"], xh, y, 51) < 1e-10
+    s.close()
+    s64.close()

@@ -158,3 +158,16 @@ def test_sampled_q1_rows_match_assembled_b0():
         row = np.zeros(B.shape[1], complex)
         row[cols] = vals
         assert np.abs(row - B[r]).max() < 1e-14 * np.abs(B).max()
+
+
+def test_sampled_p1_rows_match_assembled_b0():
+    """The row-at-a-time 2D B_0 equals the assembled operator on every row
+    of a small mesh."""
+    from gpu_util import p1_b0_rows, oracle_matrix
+    n, k = 7, 2.5
+    B = oracle_matrix(2, n, "B0", k, k).toarray()
+    allpts = [(i, j) for j in range(n + 1) for i in range(n + 1)]
+    for r, (cols, vals) in enumerate(p1_b0_rows(n, k, allpts)):
+        row = np.zeros(B.shape[1], complex)
+        row[cols] = vals
+        assert np.abs(row - B[r]).max() < 1e-14 * np.abs(B).max()
