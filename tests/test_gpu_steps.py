@@ -219,3 +219,19 @@ def test_split_column_groups_match_one_batch(prec, graphs):
         outs.append(to_host(s.precondition(to_dev(v))))
         s.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 5e-4)])
+@pytest.mark.parametrize("dim,n,levels,k,m,omega", [
+    (2, 64, 3, 6.5, 2, 2.0 / 3.0), (2, 48, 3, 4.2, 3, 0.5), (3, 16, 2, 3.5, 2, 0.6)])
+def test_preconditioner_m_and_omega(dim, n, levels, k, m, omega, prec, tol):
+    """m ceil(k) HSS steps (the paper's integer m > 1) and a Jacobi weight
+    other than 2/3, against the oracle with the same settings."""
+    s = _solver(dim, n, levels, k, k, prec, restart=4, mg_cycles=2, hss_m=m, omega=omega)
+    pr = osolver.Problem(dim, n, k, k, levels=levels, cycles=2, m=m, omega=omega)
+    assert s.n_hss == pr.hss_steps() == m * int(np.ceil(k))
+    v = W.random_complex((2, s.nodes(0)), 23)
+    z = to_host(s.precondition(to_dev(v)))
+    ref = np.stack([pr.precond(vi, inner="mg") for vi in v])
+    assert rel_l2(z, ref) < tol
+    s.close()
