@@ -173,3 +173,28 @@ def test_workspaces_of_different_sizes_on_one_handle():
         assert st["converged"] == 1
         for q, c in enumerate(cols):
             assert rel_l2(x[q], singles[c]) < 1e-12, (cols, c)
+
+
+@pytest.mark.parametrize("prec,tol_err", [("fp64", 1e-6), ("fp32", 1e-5)])
+def test_damped_problem_delta_positive(prec, tol_err):
+    """delta > 0 (B_delta with damping, delta_hat > delta): the solve and
+    the B_delta apply against the oracle."""
+    from paper_2506_18694_amd import Solver
+    from oracle import operators as ops
+    n, levels, k, delta, dh = 64, 3, 8.0, 1.5, 8.0
+    pr = osolver.Problem(2, n, k, dh, delta=delta, levels=levels)
+    s = Solver(2, n, levels, k, delta, dh, precision=prec)
+    x0 = W.random_complex((2, s.N), 61)
+    Bd = ops.b_delta(pr.K, pr.M, pr.MG, k, delta).tocsr()
+    y = to_host(s.apply("BDELTA", to_dev(x0), prec="fp64"))
+    ref = np.stack([Bd @ xi for xi in x0])
+    assert np.abs(y - ref).max() < 1e-12 * np.abs(ref).max()
+    f = W.random_complex((1, s.N), 62).real
+    b = (pr.M @ f[0])[None].astype(np.complex128)
+    x, st = s.solve(to_dev(b), tol=1e-8)
+    x = to_host(x)
+    assert st["converged"]
+    u = pr.solve_direct(b[0])
+    assert np.linalg.norm(x[0] - u) / np.linalg.norm(u) < tol_err
+    assert np.linalg.norm(b[0] - Bd @ x[0]) / np.linalg.norm(b[0]) <= 1.01e-8
+    s.close()
