@@ -198,3 +198,24 @@ def test_damped_problem_delta_positive(prec, tol_err):
     assert np.linalg.norm(x[0] - u) / np.linalg.norm(u) < tol_err
     assert np.linalg.norm(b[0] - Bd @ x[0]) / np.linalg.norm(b[0]) <= 1.01e-8
     s.close()
+
+
+@pytest.mark.parametrize("prec,tol_err", [("fp64", 1e-6), ("fp32", 1e-5)])
+def test_weak_scaling_mesh_eight_rhs(prec, tol_err):
+    """The weak-scaling setting k = n / 10 on the 128 x 128 mesh with eight
+    right-hand sides in one batch: every column against the oracle's direct
+    solve and its true residual."""
+    n, levels = 128, 5
+    k = n / 10.0
+    pr = osolver.Problem(2, n, k, k, levels=levels)
+    centres = W.seeded_centres(8, 2, 9)
+    f = np.stack([W.gaussian_nodal(2, n, c, 0.05) for c in centres])
+    b = np.stack([pr.M @ fi for fi in f]).astype(np.complex128)
+    s = _solver(2, n, levels, k, precision=prec)
+    x, st = s.solve(to_dev(b), tol=1e-8)
+    x = to_host(x)
+    assert st["converged"] == 1
+    for bi, xi in zip(b, x):
+        assert rel_l2(xi, pr.solve_direct(bi)) < tol_err
+        assert np.linalg.norm(bi - pr.B0 @ xi) / np.linalg.norm(bi) <= 1.01e-8
+    s.close()
