@@ -219,3 +219,30 @@ def test_weak_scaling_mesh_eight_rhs(prec, tol_err):
         assert rel_l2(xi, pr.solve_direct(bi)) < tol_err
         assert np.linalg.norm(bi - pr.B0 @ xi) / np.linalg.norm(bi) <= 1.01e-8
     s.close()
+
+
+def test_solve_error_paths_leave_the_handle_usable():
+    """A non-finite right-hand side, a tolerance outside (0, 1) and zero
+    columns are rejected with HELM_EINVAL; the handle then still solves."""
+    from paper_2506_18694_amd import helm
+    n, k, levels = 32, 5.0, 2
+    s = _solver(2, n, levels, k)
+    b = W.random_complex((2, s.N), 71)
+    bad = b.copy()
+    bad[1, 5] = np.nan
+    with pytest.raises(helm.HelmError) as e:
+        s.solve(to_dev(bad), tol=1e-8)
+    assert e.value.status == helm.HELM_EINVAL
+    for tol in (0.0, 1.0, -1e-3):
+        with pytest.raises(helm.HelmError) as e:
+            s.solve(to_dev(b), tol=tol)
+        assert e.value.status == helm.HELM_EINVAL
+    with pytest.raises(helm.HelmError) as e:
+        s.workspace_bytes(0)
+    assert e.value.status == helm.HELM_EINVAL
+    x, st = s.solve(to_dev(b), tol=1e-8)
+    assert st["converged"] == 1
+    pr = osolver.Problem(2, n, k, k, levels=levels)
+    for xi, bi in zip(to_host(x), b):
+        assert rel_l2(xi, pr.solve_direct(bi)) < 1e-6
+    s.close()
