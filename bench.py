@@ -2,15 +2,25 @@
 relative residual for the shifted-HSS Helmholtz solver on one MI355X.
 
 One step = one complete helm_solve (outer FP64 FGMRES, shifted-HSS
-preconditioner with ceil(k) HSS sweeps, each inner solve a fixed number of
+preconditioner with ceil(k) HSS steps, each inner solve a fixed number of
 V(2,2) cycles chosen from the measured cycle rate, all right-hand sides)
 with the load vectors already resident in HBM.
 
-Default workload: 2D P1, 1024 x 1024 right-diagonal mesh (N = 1,050,625
-nodes), k = 100, delta = 0, delta_hat = k, 8 multigrid levels, four
-Gaussian sources (sigma 0.02) at seeded uniform centres, plain complex
-FP64 on the GPU.  The same workload is also solved with FP32 multigrid and
-FP64 outer iteration, reported as `fp32_mg`.
+Headline workload (`value`): the largest one-GPU configuration, 3D Q1 on a
+256^3 hexahedral mesh (N = 257^3 = 16,974,593 nodes), k = 40, delta = 0,
+delta_hat = k, 6 multigrid levels, one Gaussian source (sigma 0.03) at a
+seeded uniform centre, plain complex FP64 on the GPU.  The same mesh is
+solved with FP32 multigrid and FP64 outer iteration (`fp32_mg`, with the
+FP64/FP32-MG DoF/s ratio), and the 2D P1 configurations 64^2 (k = 10),
+1024^2 (k = 100, four right-hand sides) and 2048^2 (k = 200) are reported
+in `workloads`, each in both precision modes with its error against the
+oracle's direct solve where the oracle can factorise the mesh (64^2 in
+process, 1024^2 in a CPU worker process that runs beside the GPU work).
+
+--steps and --warmup are caps: the run plans its solves against a
+wall-clock budget (--budget-s, measured from process start, default 450 s)
+and reports the number of headline solves it actually warmed up and timed.
+At least one full warm-up solve and one timed solve always run.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -19,8 +29,12 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
+
+T_PROC0 = time.time()
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -28,66 +42,116 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "solved DOFs/s to 1e-8 rel residual (FP32-MG vs FP64), %HBM peak; p50/p99 latency"
 PROFILES = os.path.join(ROOT, "profiles")
+HEADLINE = "q1-256-k40"
 
 
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[%6.1fs]" % (time.time() - T_PROC0), *a, file=sys.stderr, flush=True)
 
 
-# the dominant kernel: finest-level prolongation, four Jacobi sweeps (cycle
-# q's post-smoothing and cycle q+1's pre-smoothing) and the residual
-# restriction in one register-streaming pass
-DOMINANT = {"tag": "k_stream_sweeps4", "source": "kernels2d_stream.hip",
-            "desc": "finest-level prolongation + four Jacobi sweeps + residual restriction "
-                    "(k_stream_sweeps<S=4>)"}
+def elapsed():
+    return time.time() - T_PROC0
 
 
-# in 3D the timed pass is one finest-level Jacobi sweep: the z-marching
-# column-tile kernel on the interior nodes plus the boundary-node kernel
-DOMINANT_3D = ("finest-level Jacobi sweep (k_stencil3d_tile + k_stencil3d_bnd); "
-               "x, b read, x' written")
+# The dominant kernel of each mesh dimension and the source files its
+# counter record depends on.  2D: the finest-level prolongation, four Jacobi
+# sweeps (cycle q's post-smoothing and cycle q+1's pre-smoothing) and the
+# residual restriction in one register-streaming pass.  3D: one
+# finest-level Jacobi sweep, the z-marching column-tile kernel on the
+# interior nodes plus the boundary-node kernel.
+DOMINANT = {
+    2: {"tag": "k_stream_sweeps4", "sources": ("kernels2d_stream.hip", "helm_common.h", "stencil_rows.h"),
+        "desc": "finest-level prolongation + four Jacobi sweeps + residual restriction "
+                "(k_stream_sweeps<S=4>); x, b, e_c read, x', b_c written"},
+    3: {"tag": "k_stencil3d_jacobi", "sources": ("kernels3d.hip", "helm_common.h", "stencil_rows.h"),
+        "desc": "finest-level Jacobi sweep (k_stencil3d_tile + k_stencil3d_bnd); x, b read, x' written"},
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(dim):
     h = hashlib.sha256()
-    for f in (DOMINANT["source"], "helm_common.h", "stencil_rows.h"):
+    for f in DOMINANT[dim]["sources"]:
         with open(os.path.join(ROOT, "paper_2506_18694_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload, precision):
+def stored_traffic(dim, workload, precision):
     """HBM traffic per launch of the dominant kernel from committed rocprofv3
-    counter runs; null when the kernel source changed since they were taken."""
-    path = os.path.join(PROFILES, "traffic_%s_%s_%s.json" % (DOMINANT["tag"], workload, precision))
-    if workload.startswith("q1"):
-        return None
+    counter runs (FETCH_SIZE and WRITE_SIZE, copy-calibrated); null when the
+    kernel source changed since they were taken."""
+    path = os.path.join(PROFILES, "traffic_%s_%s_%s.json" % (DOMINANT[dim]["tag"], workload, precision))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(dim):
         return None
     return rec.get("bytes_per_launch")
 
 
-def run_solves(W, name, precision, steps, warmup, tol, max_outer=0, streaming=True, split=False):
-    import torch
+def host_info():
+    """Core count and CPU model of the host the CPU baseline runs on."""
+    model = platform.processor() or "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = os.cpu_count()
+    return {"nproc": affinity, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def make_solver(W, name, precision, **kw):
     from paper_2506_18694_amd import Solver
     w = W.WORKLOADS[name]
-    s = Solver(w["dim"], w["n"], w["levels"], w["k"], w["delta"], w["delta_hat"],
-               precision=precision, profile=True, max_outer=max_outer,
-               restart=max_outer if max_outer else 0, streaming=streaming, split=split)
+    return Solver(w["dim"], w["n"], w["levels"], w["k"], w["delta"], w["delta_hat"],
+                  precision=precision, **kw)
+
+
+def measure(W, name, precision, warmup_max, steps_max, tol, deadline_fn=None, full_warmup=True,
+            streaming=True, split=False, keep_x=False):
+    """Warm up and time complete solves of one workload on one handle.
+
+    full_warmup: the first warm-up is a complete solve (its time estimates
+    a step); otherwise the warm-up is one preconditioner application on the
+    same handle and workspace (it measures the cycle rate and the segment
+    heights that the timed solve then reuses).  deadline_fn(t_solve) returns
+    how many more solves of t_solve seconds fit the budget."""
+    import torch
+    s = make_solver(W, name, precision, profile=True, streaming=streaming, split=split)
     f = torch.from_numpy(W.workload_sources(name)).cuda().contiguous()
     b = s.load_nodal(f)
     x = torch.empty_like(b)
     ws = s.workspace(b.shape[0])
     log("[bench] %s %s: N=%d nrhs=%d workspace %.1f GB" % (name, precision, s.N, b.shape[0],
                                                            ws.numel() / 1e9))
-    for i in range(warmup):
+    t_est = None
+    warm = 0
+    if full_warmup:
         _, st = s.solve(b, x, tol=tol, workspace=ws)
-        log("[bench] warmup %d: %.1f ms, outer its %d, true rel res %.2e"
-            % (i, st["solve_ms"], st["outer_its"], st["true_rel_residual"]))
+        warm = 1
+        t_est = st["solve_ms"] / 1e3
+        log("[bench] warmup 0: %.1f ms, outer its %d, true rel res %.2e"
+            % (st["solve_ms"], st["outer_its"], st["true_rel_residual"]))
+    else:
+        _ = s.precondition(b)
+        torch.cuda.synchronize()
+        log("[bench] warmup: one preconditioner application")
+    steps = steps_max
+    if deadline_fn is not None and t_est is not None:
+        fit = deadline_fn(t_est)
+        steps = max(1, min(steps_max, fit))
+        extra = max(0, min(warmup_max - warm, fit - steps))
+        for i in range(extra):
+            _, st = s.solve(b, x, tol=tol, workspace=ws)
+            warm += 1
+            log("[bench] warmup %d: %.1f ms" % (warm - 1, st["solve_ms"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -97,36 +161,127 @@ def run_solves(W, name, precision, steps, warmup, tol, max_outer=0, streaming=Tr
         log("[bench] step %d: %.1f ms, outer its %d, true rel res %.2e"
             % (i, st["solve_ms"], st["outer_its"], st["true_rel_residual"]))
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    el = time.perf_counter() - t0
     ok = all(st["converged"] == 1 and st["true_rel_residual"] <= tol for st in stats)
+    xh = x.cpu().numpy() if keep_x else None
+    N, nrhs = s.N, b.shape[0]
     s.close()
-    return dict(N=s.N, nrhs=b.shape[0], elapsed=elapsed, stats=stats, ok=ok, w=w)
+    s._ws.clear()
+    del ws, b, x, s
+    torch.cuda.empty_cache()
+    ms = el / steps * 1e3
+    last = stats[-1]
+    return dict(N=N, nrhs=nrhs, elapsed=el, steps=steps, warmup=warm, stats=stats, ok=ok,
+                ms=ms, value=N * nrhs / (ms / 1e3), x=xh,
+                summary={"value": N * nrhs / (ms / 1e3), "ms_per_step": ms, "steps": steps,
+                         "warmup": warm if full_warmup else "one preconditioner application",
+                         "outer_its": max(st["outer_its"] for st in stats),
+                         "mg_cycles": last["mg_cycles"], "hss_steps": last["hss_steps"],
+                         "vcycle_rate": last["vcycle_rate"],
+                         "true_rel_residual": max(st["true_rel_residual"] for st in stats),
+                         "converged": ok})
 
 
-def cpu_baseline(W, name, outer_its, cycles, sample_steps):
-    """The oracle's HSS step (correction form, `cycles` CSR V(2,2) cycles per
-    inner solve, as the GPU run used) timed on the host for one right-hand
-    side, extrapolated to the full solve with the GPU's outer iteration count
-    (the oracle's own FGMRES orthogonalisation is left out, which flatters
-    the CPU)."""
-    from oracle import solver as osolver, hss
+def roofline(dim, name, precision, stats):
+    """HBM roofline of the dominant kernel from the HIP-event timings that
+    the timed solves took of its launches (every tenth HSS step)."""
+    sw_ms = sum(st["sweep_ms"] for st in stats)
+    sw_n = sum(st["sweep_launches"] for st in stats)
+    sw_b = sum(st["sweep_bytes"] for st in stats)
+    achieved = sw_b / (sw_ms / 1e3) / 1e9 if sw_ms > 0 else None
+    per_launch = sw_b / sw_n if sw_n else None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": stored_traffic(dim, name, precision),
+            "kernel": DOMINANT[dim]["desc"], "bytes_per_launch": per_launch,
+            "avg_launch_us": sw_ms / sw_n * 1e3 if sw_n else None, "launches_timed": sw_n}
+
+
+# ---------------------------------------------------------------- oracle side --
+def _oracle_direct_worker(name, out_path):
+    """CPU worker: the oracle's direct solves B_0 u = b of a workload's
+    right-hand sides (sparse LU), saved for the error of the GPU solves."""
+    import numpy as np
+    from oracle import solver as osolver
+    import workloads as W
     w = W.WORKLOADS[name]
-    pr = osolver.Problem(w["dim"], w["n"], w["k"], w["delta_hat"], levels=w["levels"],
-                         cycles=cycles)
-    f = W.workload_sources(name)[0]
-    R = pr.M @ f
+    pr = osolver.Problem(w["dim"], w["n"], w["k"], w["delta_hat"], levels=1)
+    f = W.workload_sources(name)
+    U = np.stack([pr.solve_direct((pr.M @ fi).astype(np.complex128)) for fi in f])
+    np.save(out_path + ".tmp.npy", U)
+    os.replace(out_path + ".tmp.npy", out_path)
+
+
+def start_oracle_worker(name, tmpdir):
+    import multiprocessing as mp
+    out = os.path.join(tmpdir, "oracle_%s.npy" % name)
+    if os.path.exists(out):
+        os.remove(out)
+    p = mp.get_context("spawn").Process(target=_oracle_direct_worker, args=(name, out), daemon=True)
+    p.start()
+    return p, out
+
+
+def oracle_error(x, u):
+    """Relative l2 error of each column of x against the oracle's u (max)."""
+    import numpy as np
+    return float(max(np.linalg.norm(xi - ui) / np.linalg.norm(ui) for xi, ui in zip(x, u)))
+
+
+def _baseline_column_worker(args):
+    """One right-hand side's oracle HSS steps, timed (CPU worker)."""
+    dim, n, k, dh, levels, cycles, centre, sigma, steps = args
+    import numpy as np
+    from oracle import solver as osolver, hss
+    import workloads as W
+    pr = osolver.Problem(dim, n, k, dh, levels=levels, cycles=cycles)
     _ = pr.hierarchy
+    R = pr.M @ W.gaussian_nodal(dim, n, centre, sigma)
     t0 = time.perf_counter()
-    hss.hss_correction(pr.Bdh, R, w["k"], sample_steps, pr.mg_solve)
-    t_step = (time.perf_counter() - t0) / sample_steps
-    nrhs = w["nrhs"]
-    t_solve = nrhs * outer_its * pr.hss_steps() * t_step
-    N = (w["n"] + 1) ** w["dim"]
-    return {"value": N * nrhs / t_solve, "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": "%d HSS steps (%d CSR V(2,2) cycles each) for 1 of %d right-hand sides on "
-                      "the %s mesh, %.3f s per step, extrapolated to %d outer its x %d steps x "
-                      "%d rhs" % (sample_steps, cycles, nrhs, name, t_step, outer_its,
-                                  pr.hss_steps(), nrhs)}
+    hss.hss_correction(pr.Bdh, R, k, steps, pr.mg_solve)
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(W, name, outer_its, cycles, sample_steps, info):
+    """The oracle (plain CSR, complex FP64) timed on the host: its HSS step
+    in correction form with the same number of CSR V(2,2) cycles per inner
+    solve as the GPU run, extrapolated to the whole solve with the GPU's
+    outer iteration count (the oracle's own FGMRES orthogonalisation is left
+    out, which flatters the CPU).  Independent right-hand sides run in
+    parallel worker processes, one per column (at most one per core).  A 3D
+    mesh too large for the oracle's assembly within the sample's budget is
+    sampled on a 64^3 mesh with the same k, delta_hat, cycles and coarsest
+    mesh, and its cost per node and step carried over (the oracle's CSR
+    passes cost the same per node at any size)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    w = W.WORKLOADS[name]
+    dim, nrhs = w["dim"], w["nrhs"]
+    n_s, lev_s = w["n"], w["levels"]
+    if dim == 3 and w["n"] > 64:
+        n_s = 64
+        lev_s = w["levels"] - 2
+    centres = W.workload_centres(name)
+    jobs = [(dim, n_s, w["k"], w["delta_hat"], lev_s, cycles, tuple(c), w["sigma"], sample_steps)
+            for c in centres]
+    workers = max(1, min(len(jobs), info["nproc"]))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        t_steps = list(ex.map(_baseline_column_worker, jobs))
+    import math
+    hss_steps = int(math.ceil(w["k"]))
+    N = (w["n"] + 1) ** dim
+    N_s = (n_s + 1) ** dim
+    t_step = sum(t_steps) / len(t_steps) * (N / N_s)  # one column's HSS step at full size
+    # the columns run concurrently on `workers` cores
+    t_solve = outer_its * hss_steps * t_step * math.ceil(nrhs / workers)
+    return {"value": N * nrhs / t_solve, "unit": "DoF/s", "cores": workers,
+            "host_cores": info["nproc"], "cpu_model": info["cpu_model"], "kind": "oracle",
+            "sample": "%d HSS steps (%d CSR V(2,2) cycles each) per right-hand side on the %s "
+                      "mesh%s, %d column(s) on %d core(s), %.3f s per full-size step; "
+                      "extrapolated to %d outer its x %d HSS steps"
+                      % (sample_steps, cycles, name,
+                         (" reduced to %d^3 (%d levels), cost per node carried over" % (n_s, lev_s))
+                         if n_s != w["n"] else "", nrhs, workers, t_step, outer_its, hss_steps)}
 
 
 def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1):
@@ -340,9 +495,20 @@ def run_paper(W, ks, precision, rtol_ref="r0", cycle="v", outers=("fgmres", "ric
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="p1-1024-k100")
+    ap.add_argument("--steps", type=int, default=1,
+                    help="cap on the timed headline solves (the wall-clock budget may allow fewer)")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="cap on the headline's full warm-up solves (at least one runs)")
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="wall-clock budget of the whole run in seconds, from process start")
+    ap.add_argument("--workload", default=HEADLINE)
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="precision mode of the headline solves (the other mode is reported "
+                         "beside them)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="skip the 2D configurations")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="skip the error of the 2D solves against the oracle's direct solve")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--split", action="store_true",
@@ -352,9 +518,10 @@ def main():
                     help="run the large 2D levels with the LDS-tiled kernels instead of the "
                          "register-streaming ones (for comparison)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--profile-run", action="store_true",
-                    help="short run for counter collection: 3 outer iterations, no extras")
+                    help="short run for counter collection: 3 outer iterations of the "
+                         "headline workload, no extras")
     ap.add_argument("--serving", action="store_true",
                     help="run the continuous-batching serving workload instead (one JSON line)")
     ap.add_argument("--requests", type=int, default=64)
@@ -444,63 +611,129 @@ def main():
                "serving": res}
         print(json.dumps(out), flush=True)
         return
-    name = args.workload
-    prec = W.WORKLOADS[name]["precision"]
-    main_prec = "fp64" if prec == "fp64" else "fp32"
     if args.profile_run:
-        args.no_fp32 = args.no_cpu_baseline = True
-    r = run_solves(W, name, main_prec, args.steps, args.warmup, args.tol,
-                   max_outer=3 if args.profile_run else 0, streaming=not args.lds_kernels,
-                   split=args.split)
-    ms = r["elapsed"] / args.steps * 1e3
-    value = r["N"] * r["nrhs"] / (ms / 1e3)
-    sw_ms = sum(st["sweep_ms"] for st in r["stats"])
-    sw_n = sum(st["sweep_launches"] for st in r["stats"])
-    sw_b = sum(st["sweep_bytes"] for st in r["stats"])
-    achieved = sw_b / (sw_ms / 1e3) / 1e9 if sw_ms > 0 else None
-    per_launch = sw_b / sw_n if sw_n else None
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": stored_traffic(name, main_prec),
-            "kernel": DOMINANT["desc"] if r["w"]["dim"] == 2 else DOMINANT_3D,
-            "bytes_per_launch": per_launch,
-            "avg_launch_us": sw_ms / sw_n * 1e3 if sw_n else None}
-    w = r["w"]
-    out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        # counter collection: a handle capped at 3 outer iterations, eager
+        w = W.WORKLOADS[args.workload]
+        prec = args.precision
+        s = make_solver(W, args.workload, prec, profile=True, max_outer=3, restart=3,
+                        streaming=not args.lds_kernels)
+        f = torch.from_numpy(W.workload_sources(args.workload)).cuda().contiguous()
+        b = s.load_nodal(f)
+        _, st = s.solve(b, tol=args.tol)
+        torch.cuda.synchronize()
+        log("[bench] profile run: %d outer its, %.1f ms" % (st["outer_its"], st["solve_ms"]))
+        print(json.dumps({"profile_run": args.workload, "precision": prec,
+                          "outer_its": st["outer_its"], "solve_ms": st["solve_ms"],
+                          "roofline": roofline(w["dim"], args.workload, prec, [st])}), flush=True)
+        return
+    # ---- the default run: headline + the other configurations -----------------
+    import tempfile
+    budget = args.budget_s
+    info = host_info()
+    tmpdir = tempfile.mkdtemp(prefix="helm_bench_")
+    w_head = W.WORKLOADS[args.workload]
+    head_prec = args.precision
+    other = [] if args.only_headline else [n for n in ("p1-64-k10", "p1-1024-k100", "p1-2048-k200")
+                                           if n != args.workload]
+    # the 1024^2 direct solve (about a minute of one core) runs beside the GPU work
+    worker = None
+    if "p1-1024-k100" in other and not args.no_oracle_error:
+        worker = start_oracle_worker("p1-1024-k100", tmpdir)
+        log("[bench] oracle direct-solve worker started for p1-1024-k100")
+    # time the rest of the run needs after the headline's FP64 solves, in
+    # units of one headline solve (FP32-MG: a cheaper solve, no full warm-up)
+    # plus the fixed-size parts (2D configurations, CPU baseline, margin)
+    fixed_rest = (0 if args.only_headline else 75.0) + (0 if args.no_cpu_baseline else 25.0) + 20.0
+
+    def fits(t_solve):
+        rest = fixed_rest + (0 if args.no_fp32 else 1.0 * t_solve)
+        return int(max(0.0, budget - elapsed() - rest) // max(t_solve, 1e-3))
+
+    r = measure(W, args.workload, head_prec, args.warmup, args.steps, args.tol, deadline_fn=fits,
+                streaming=not args.lds_kernels, split=args.split, keep_x=not args.no_fp32)
+    dim = w_head["dim"]
+    out = {"metric": METRIC, "value": r["value"], "unit": "DoF/s", "n_gpus": 1,
+           "steps": r["steps"], "warmup": r["warmup"], "ms_per_step": r["ms"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if main_prec == "fp64" else "f32+f64",
-           "data": "synthetic",
-           "config": {"workload": name, "dim": w["dim"], "n": w["n"], "dofs": r["N"],
-                      "nrhs": r["nrhs"], "k": w["k"], "delta_hat": w["delta_hat"],
-                      "levels": w["levels"], "precision": main_prec, "tol": args.tol,
-                      "outer_its": max(st["outer_its"] for st in r["stats"]),
-                      "hss_steps": r["stats"][0]["hss_steps"],
-                      "mg_cycles": r["stats"][0]["mg_cycles"],
-                      "vcycle_rate": r["stats"][0]["vcycle_rate"],
-                      "true_rel_residual": max(st["true_rel_residual"] for st in r["stats"]),
-                      "converged": r["ok"]},
-           "roofline": roof,
-           # where a solve's time goes: device time inside the preconditioner
-           # (HSS loop) against the whole solve's wall time
+           "dtype": "f64" if head_prec == "fp64" else "f32+f64", "data": "synthetic",
+           "config": {"workload": args.workload, "dim": dim, "n": w_head["n"], "dofs": r["N"],
+                      "nrhs": r["nrhs"], "k": w_head["k"], "delta_hat": w_head["delta_hat"],
+                      "levels": w_head["levels"], "precision": head_prec, "tol": args.tol,
+                      "outer_its": r["summary"]["outer_its"],
+                      "hss_steps": r["summary"]["hss_steps"],
+                      "mg_cycles": r["summary"]["mg_cycles"],
+                      "vcycle_rate": r["summary"]["vcycle_rate"],
+                      "true_rel_residual": r["summary"]["true_rel_residual"],
+                      "converged": r["ok"], "budget_s": budget,
+                      "requested_steps": args.steps, "requested_warmup": args.warmup},
+           "roofline": roofline(dim, args.workload, head_prec, r["stats"]),
            "breakdown": {"solve_ms": sum(st["solve_ms"] for st in r["stats"]) / len(r["stats"]),
                          "precond_ms": sum(st["precond_ms"] for st in r["stats"]) / len(r["stats"])}}
-    if not args.no_fp32 and main_prec == "fp64":
-        r32 = run_solves(W, name, "fp32", 1, 1, args.tol, streaming=not args.lds_kernels,
-                         split=args.split)
-        ms32 = r32["elapsed"] * 1e3
-        v32 = r32["N"] * r32["nrhs"] / (ms32 / 1e3)
-        s32 = r32["stats"][0]
-        out["fp32_mg"] = {"value": v32, "ms_per_step": ms32, "ratio_vs_fp64": v32 / value,
-                          "outer_its": s32["outer_its"],
-                          "true_rel_residual": s32["true_rel_residual"],
-                          "sweep_GBs": s32["sweep_bytes"] / (s32["sweep_ms"] / 1e3) / 1e9
-                          if s32["sweep_ms"] > 0 else None,
-                          "converged": r32["ok"]}
+    if not args.no_fp32:
+        import numpy as np
+        other_prec = "fp32" if head_prec == "fp64" else "fp64"
+        r2 = measure(W, args.workload, other_prec, 1, 1, args.tol, full_warmup=False,
+                     streaming=not args.lds_kernels, split=args.split, keep_x=True)
+        sub = dict(r2["summary"])
+        a, b = (r["x"], r2["x"]) if head_prec == "fp64" else (r2["x"], r["x"])
+        sub["rel_l2_vs_fp64_solution"] = oracle_error(b, a)
+        if head_prec == "fp64":
+            sub["ratio_vs_fp64"] = r2["value"] / r["value"]
+            out["fp32_mg"] = sub
+        else:
+            sub["ratio_fp32mg_over_fp64"] = r["value"] / r2["value"]
+            out["fp64"] = sub
+        del a, b
+    r.pop("x", None)
+    # ---- the 2D configurations: both precision modes, error vs the oracle ------
+    subs = {}
+    for name in other:
+        if elapsed() > budget - fixed_rest + 60.0:
+            log("[bench] skipping %s: budget" % name)
+            subs[name] = {"skipped": "wall-clock budget"}
+            continue
+        import numpy as np
+        w = W.WORKLOADS[name]
+        ent = {"dim": w["dim"], "n": w["n"], "dofs": (w["n"] + 1) ** w["dim"], "nrhs": w["nrhs"],
+               "k": w["k"], "levels": w["levels"]}
+        xs = {}
+        for prec in ("fp64", "fp32"):
+            m = measure(W, name, prec, 1, 1, args.tol, full_warmup=False,
+                        streaming=not args.lds_kernels, keep_x=True)
+            xs[prec] = m["x"]
+            ent["fp64" if prec == "fp64" else "fp32_mg"] = m["summary"]
+        ent["ratio_fp32mg_vs_fp64"] = ent["fp32_mg"]["value"] / ent["fp64"]["value"]
+        ent["fp32mg_rel_l2_vs_fp64_solution"] = oracle_error(xs["fp32"], xs["fp64"])
+        if not args.no_oracle_error:
+            U = None
+            if name == "p1-64-k10":
+                from oracle import solver as osolver
+                pr = osolver.Problem(2, w["n"], w["k"], w["delta_hat"], levels=1)
+                U = np.stack([pr.solve_direct((pr.M @ fi).astype(np.complex128))
+                              for fi in W.workload_sources(name)])
+            elif worker is not None and name == "p1-1024-k100":
+                p, path = worker
+                p.join(timeout=max(1.0, budget - elapsed() - fixed_rest))
+                if os.path.exists(path):
+                    U = np.load(path)
+            if U is not None:
+                ent["rel_l2_error_vs_oracle_direct"] = {"fp64": oracle_error(xs["fp64"], U),
+                                                        "fp32_mg": oracle_error(xs["fp32"], U)}
+            else:
+                ent["rel_l2_error_vs_oracle_direct"] = None
+        subs[name] = ent
+        log("[bench] %s: fp64 %.3g DoF/s, fp32-mg %.3g DoF/s (ratio %.2f)"
+            % (name, ent["fp64"]["value"], ent["fp32_mg"]["value"], ent["ratio_fp32mg_vs_fp64"]))
+    if subs:
+        out["workloads"] = subs
+    if worker is not None and worker[0].is_alive():
+        worker[0].terminate()
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline sample ...")
-        out["cpu_baseline"] = cpu_baseline(W, name, out["config"]["outer_its"],
-                                           out["config"]["mg_cycles"], args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(W, args.workload, out["config"]["outer_its"],
+                                           out["config"]["mg_cycles"], args.cpu_sample_steps, info)
+    out["host"] = info
+    out["wall_s"] = elapsed()
     print(json.dumps(out), flush=True)
 
 

@@ -18,9 +18,10 @@
  * eq. (HSSpc primal)) with delta replaced by delta_hat > delta:
  * m*ceil(k) gamma=k HSS steps from u_0 = 0, each inner solve with
  *     L = K + (dh^2 - k^2 - 2i dh k^2) M + (dh - i k^2) M_Gamma
- * approximated by one geometric-multigrid V(nu1,nu2) cycle with scaled
- * Jacobi smoothing (Sec. 5.3), FE interpolation / its transpose as
- * transfers, and an FP64 dense solve on the coarsest mesh.
+ * approximated by q geometric-multigrid V(nu1,nu2) cycles (q >= 2, chosen
+ * per handle from the measured cycle rate unless helm_opts.mg_cycles sets
+ * it) with scaled Jacobi smoothing (Sec. 5.3), FE interpolation / its
+ * transpose as transfers, and an FP64 dense solve on the coarsest mesh.
  *
  * Data layout (all vectors): complex, interleaved (re, im), one column per
  * right-hand side, column-major [nrhs][N]; nodes lexicographic,

@@ -49,12 +49,13 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def q1_b0_rows(n, k, ijk):
-    """Rows of the 3D Q1 operator B_0 = K - k^2 M - i k M_Gamma (every face
+def q1_rows(n, abc, ijk):
+    """Rows of the 3D Q1 operator a K + b M + c M_Gamma (every face
     Sommerfeld) for the nodes ijk = [(i, j, l), ...], built one row at a
     time from the oracle's element and face matrices, so that a mesh too
     large to assemble can be checked on sampled nodes.  Returns a list of
     (columns, values)."""
+    a_, b_, c_ = abc
     h = 1.0 / n
     kl, ml = fem.q1_element_matrices(h)
     gl = fem.q1_face_matrix(h)
@@ -71,7 +72,7 @@ def q1_b0_rows(n, k, ijk):
                     a = (i - p) + 2 * (j - q) + 4 * (l - r)
                     for b in range(8):
                         col = idx(p + (b & 1), q + ((b >> 1) & 1), r + ((b >> 2) & 1))
-                        acc[col] = acc.get(col, 0.0) + kl[a, b] - k * k * ml[a, b]
+                        acc[col] = acc.get(col, 0.0) + a_ * kl[a, b] + b_ * ml[a, b]
         # boundary faces: x faces span (y, z), y faces (x, z), z faces (x, y)
         for ax, (u, v) in ((0, (1, 2)), (1, (0, 2)), (2, (0, 1))):
             if c[ax] not in (0, n):
@@ -85,10 +86,71 @@ def q1_b0_rows(n, k, ijk):
                         node = list(c)
                         node[u], node[v] = au + (m & 1), bv + (m >> 1)
                         col = idx(*node)
-                        acc[col] = acc.get(col, 0.0) - 1j * k * gl[loc, m]
+                        acc[col] = acc.get(col, 0.0) + c_ * gl[loc, m]
         cols = np.array(sorted(acc), dtype=np.int64)
-        rows.append((cols, np.array([acc[cc] for cc in cols], dtype=np.complex128)))
+        rows.append((cols, np.array([complex(acc[cc]) for cc in cols], dtype=np.complex128)))
     return rows
+
+
+def q1_b0_rows(n, k, ijk):
+    """Rows of B_0 = K - k^2 M - i k M_Gamma (see q1_rows)."""
+    return q1_rows(n, (1.0, -k * k, -1j * k), ijk)
+
+
+def row_apply(rows, x):
+    """(A x) at the rows' nodes."""
+    return np.array([vals @ x[cols] for cols, vals in rows])
+
+
+def row_diag(rows, ijk, n):
+    """The diagonal entries of the rows of nodes ijk."""
+    out = []
+    for (cols, vals), (i, j, l) in zip(rows, ijk):
+        t = i + (n + 1) * (j + (n + 1) * l)
+        out.append(vals[np.searchsorted(cols, t)])
+    return np.array(out)
+
+
+def q1_prolong_row(nf, node):
+    """Row of the trilinear interpolation P (n/2 mesh -> nf mesh) at fine
+    node (i, j, l): the coarse basis functions evaluated at the node with
+    the oracle's Q1 basis.  Returns (coarse columns, weights)."""
+    nc = nf // 2
+    i, j, l = node
+    cell = [min(v // 2, nc - 1) for v in (i, j, l)]
+    loc = [v / 2.0 - cv for v, cv in zip((i, j, l), cell)]
+    val, _ = fem._q1_basis(*loc)
+    cols, w = [], []
+    for a in range(8):
+        if abs(val[a]) < 1e-14:
+            continue
+        I, J, L = cell[0] + (a & 1), cell[1] + ((a >> 1) & 1), cell[2] + ((a >> 2) & 1)
+        cols.append(I + (nc + 1) * (J + (nc + 1) * L))
+        w.append(val[a])
+    return np.array(cols, dtype=np.int64), np.array(w)
+
+
+def q1_restrict_rows(nf, coarse_nodes):
+    """Rows of P^T at coarse nodes (I, J, L): the fine nodes within one of
+    (2I, 2J, 2L) on every axis with their weights P[f, C]."""
+    nc = nf // 2
+    out = []
+    for (I, J, L) in coarse_nodes:
+        C = I + (nc + 1) * (J + (nc + 1) * L)
+        fine, w = [], []
+        for dl in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    f = (2 * I + di, 2 * J + dj, 2 * L + dl)
+                    if min(f) < 0 or max(f) > nf:
+                        continue
+                    cols, ww = q1_prolong_row(nf, f)
+                    hit = np.nonzero(cols == C)[0]
+                    if hit.size:
+                        fine.append(f)
+                        w.append(ww[hit[0]])
+        out.append((fine, np.array(w)))
+    return out
 
 
 def sample_nodes_3d(n, count, seed):

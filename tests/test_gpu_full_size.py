@@ -8,10 +8,12 @@ LDS-resident small levels).
 every output of the operator apply, of one V-cycle and of two shifted-HSS
 steps is compared with the oracle element by element; the full solve to
 1e-8 is checked through its true residual, recomputed with the oracle's
-assembled B_0 (the direct solve of a million complex unknowns is left to
-the smaller cases).  3D Q1 256^3, k = 40: the operator apply on sampled
-nodes (corners, edges, faces and random interior nodes), the rows built
-from the oracle's element matrices.  2D P1 2048 x 2048, k = 200 (too large
+assembled B_0, and through its error against the oracle's sparse direct
+solution (1e-6 FP64, 1e-5 FP32 multigrid); the FP32-multigrid
+preconditioner is shown to compute in FP32.  3D Q1 256^3, k = 40: the
+operator apply on sampled nodes (corners, edges, faces and random interior
+nodes), the rows built from the oracle's element matrices (the other 3D
+steps and the 3D solve: test_gpu_full_size_3d.py).  2D P1 2048 x 2048, k = 200 (too large
 for the oracle's assembly in a test): the B_0 apply on sampled rows, and
 the FP32-multigrid solve through the residual of the library's B_0 apply,
 whose sampled rows are checked against the oracle on the solution itself.
@@ -91,8 +93,21 @@ def test_headline_two_hss_steps(head, prec, tol):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_headline_solve_true_residual(head, prec):
+@pytest.fixture(scope="module")
+def head_direct(head):
+    """The oracle's sparse direct solutions u = B_0^{-1} b of the four
+    right-hand sides (about a minute of one core)."""
+    w, pr = head
+    return np.stack([pr.solve_direct((pr.M @ fi).astype(np.complex128))
+                     for fi in W.workload_sources(HEAD)])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,err_tol", [("fp64", 1e-6), ("fp32", 1e-5)])
+def test_headline_solve_true_residual(head, head_direct, prec, err_tol):
+    """The 1e-8 solve: converged, true residual with the oracle's CSR B_0,
+    and each column's relative l2 error against the oracle's direct
+    solution (1e-6 for the FP64 path, 1e-5 for FP32 multigrid)."""
     import torch
     w, pr = head
     s = _bench_solver(HEAD, prec)
@@ -101,8 +116,9 @@ def test_headline_solve_true_residual(head, prec):
     x, st = s.solve(b, tol=1e-8)
     assert st["converged"]
     bh, xh = to_host(b), to_host(x)
-    for bi, xi in zip(bh, xh):
+    for bi, xi, ui in zip(bh, xh, head_direct):
         assert np.linalg.norm(bi - pr.B0 @ xi) / np.linalg.norm(bi) <= 1.01e-8
+        assert rel_l2(xi, ui) <= err_tol
     # the load vector itself against the oracle's mass matrix
     fh = W.workload_sources(HEAD)
     assert rel_err(bh, np.stack([pr.M @ fi for fi in fh])) < 1e-12
@@ -163,3 +179,25 @@ def test_2048_fp32_solve_residual():
     assert _sampled_2d(w["n"], w["k"], xh, y, 51) < 1e-10
     s.close()
     s64.close()
+
+
+def test_headline_fp32_mg_runs_in_fp32(head):
+    """The FP32-multigrid preconditioner really computes in FP32: on the same
+    input its output differs from the FP64 preconditioner's by FP32 rounding
+    (far above FP64 round-off, far below the method's own error), and every
+    value it returns is an FP32 number (the directions are stored in FP32
+    and promoted exactly)."""
+    import torch
+    w, pr = head
+    v = to_dev(W.random_complex((w["nrhs"], (w["n"] + 1) ** 2), 53))
+    z = {}
+    for prec in ("fp64", "fp32"):
+        s = _bench_solver(HEAD, prec, mg_cycles=3)
+        z[prec] = s.precondition(v)
+        torch.cuda.synchronize()
+        s.close()
+    d = float(torch.linalg.vector_norm(z["fp32"] - z["fp64"]) / torch.linalg.vector_norm(z["fp64"]))
+    assert 1e-9 < d < 1e-3, d
+    z32 = z["fp32"]
+    assert torch.equal(z32.to(torch.complex64).to(torch.complex128), z32)
+    assert not torch.equal(z["fp64"].to(torch.complex64).to(torch.complex128), z["fp64"])

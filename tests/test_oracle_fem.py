@@ -160,6 +160,45 @@ def test_sampled_q1_rows_match_assembled_b0():
         assert np.abs(row - B[r]).max() < 1e-14 * np.abs(B).max()
 
 
+def test_sampled_q1_rows_match_assembled_operators():
+    """The row builder for any a K + b M + c M_Gamma (here L and B_shift of
+    the HSS step) equals the assembled operator on every row of a small mesh,
+    and its diagonal is the Jacobi diagonal."""
+    from gpu_util import q1_rows, row_apply, row_diag
+    from oracle import operators as ops
+    n, k, dh = 4, 3.5, 2.0
+    K, M, MG = fem.assemble(3, n)
+    allpts = [(i, j, l) for l in range(n + 1) for j in range(n + 1) for i in range(n + 1)]
+    x = np.random.default_rng(5).standard_normal((n + 1) ** 3) * (1 + 1j)
+    for name, delta in (("L", dh), ("B", dh)):
+        abc = ops.coefficients(name, k, delta)
+        A = ops.combine(K, M, MG, abc)
+        rows = q1_rows(n, abc, allpts)
+        assert np.abs(row_apply(rows, x) - A @ x).max() < 1e-13 * np.abs(A @ x).max()
+        assert np.abs(row_diag(rows, allpts, n) - A.diagonal()).max() < 1e-14 * np.abs(A.diagonal()).max()
+
+
+def test_sampled_q1_transfer_rows_match_prolongation():
+    """Rows of P from the oracle's Q1 basis, and rows of P^T gathered from
+    them, equal the oracle's assembled trilinear prolongation."""
+    from gpu_util import q1_prolong_row, q1_restrict_rows
+    n = 6
+    nc = n // 2
+    P = fem.prolongation_3d(n).toarray()
+    for l in range(n + 1):
+        for j in range(n + 1):
+            for i in range(n + 1):
+                cols, w = q1_prolong_row(n, (i, j, l))
+                row = np.zeros(P.shape[1])
+                row[cols] = w
+                assert np.abs(row - P[i + (n + 1) * (j + (n + 1) * l)]).max() < 1e-15
+    cpts = [(I, J, L) for L in range(nc + 1) for J in range(nc + 1) for I in range(nc + 1)]
+    for C, (fine, w) in enumerate(q1_restrict_rows(n, cpts)):
+        col = np.zeros(P.shape[0])
+        col[[f[0] + (n + 1) * (f[1] + (n + 1) * f[2]) for f in fine]] = w
+        assert np.abs(col - P[:, C]).max() < 1e-15
+
+
 def test_sampled_p1_rows_match_assembled_b0():
     """The row-at-a-time 2D B_0 equals the assembled operator on every row
     of a small mesh."""
