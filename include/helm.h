@@ -343,6 +343,25 @@ int helm_coarse_solve(helm_t* h, int prec, const void* b, void* x, int nrhs);
 int helm_vcycle(helm_t* h, int prec, const void* b, void* x, int nrhs,
                 void* workspace);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the cycle
+ * of helm_vcycle with the level vectors in a scratch array the library
+ * holds on each device (HELM_NOALLOC_SCRATCH_BYTES, kept until the process
+ * ends) instead of a workspace.  It calls no hipMalloc, hipFree or other
+ * allocating routine; segment heights not measured yet on this thread come
+ * from the library's model (no timing launches).  Same arguments, layout
+ * and result as helm_vcycle, bit for bit; b and x are device vectors on
+ * the current device, which must be the handle's.  Every call on a device
+ * shares that device's scratch: calls that overlap on one device (two
+ * streams, two threads) race and give wrong results.  The scratch needs no
+ * clearing (every level vector is written before it is read).
+ * Errors: HELM_EINVAL for the arguments helm_vcycle rejects, a current
+ * device other than the handle's, or a mesh and column count whose level
+ * vectors exceed HELM_NOALLOC_SCRATCH_BYTES (helm_last_error gives the
+ * bytes needed); HELM_ENOTSUP with HELM_CYCLE_W_GMRES; HELM_EDEVICE. */
+#define HELM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int helm_vcycle_noalloc(helm_t* h, int prec, const void* b, void* x, int nrhs);
+
 /* Shifted-HSS preconditioner z = B~^{-1} v (Definition "Shifted HSS
  * iteration for the primal system"), correction form, in the handle's
  * precision mode.  v, z: complex FP64 [nrhs][helm_vector_length(h)]; the

@@ -25,6 +25,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1663,6 +1664,97 @@ int helm_hss_history(helm_t* h, const void* v, void* z, int nrhs, void* workspac
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(h->stream));
+    } catch (const DevErr&) {
+        return HELM_EDEVICE;
+    }
+    return HELM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- cycle without allocation --
+// helm_vcycle_noalloc keeps the cycle's level vectors in this file-scope
+// device array instead of a caller workspace.  Every device the call runs on
+// holds its own copy, at its own address, until the process ends; in host
+// code the name is only a stand-in, so the address is looked up once per
+// device and that pointer is what the kernels receive.
+static __device__ __align__(256) unsigned char scratch[HELM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_SCRATCH_DEVICES] = {};
+
+// device address of `scratch` on device dev (current on the calling thread)
+void* scratch_on(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// the level vectors one cycle on level 0 uses: level 0's second buffer t,
+// then b, x and t of every coarser level (the same roles as in layout())
+Layout layout_cycle(const helm_t* h, int nrhs) {
+    Layout L{};
+    L.cap = nrhs;
+    size_t off = 0;
+    const size_t smg = h->prec == HELM_FP64 ? sizeof(cxd) : sizeof(cxf);
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += up(bytes);
+        return o;
+    };
+    L.mg_t[0] = take(smg * nrhs * h->Nl[0]);
+    for (int l = 1; l < h->levels; ++l) {
+        L.mg_b[l] = take(smg * nrhs * h->Nl[l]);
+        L.mg_x[l] = take(smg * nrhs * h->Nl[l]);
+        L.mg_t[l] = take(smg * nrhs * h->Nl[l]);
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int helm_vcycle_noalloc(helm_t* h, int prec, const void* b, void* x, int nrhs) {
+    if (!h || !b || !x || nrhs < 1) return HELM_EINVAL;
+    if (prec != HELM_FP64 && prec != HELM_FP32_MG) return HELM_EINVAL;
+    if (prec != h->prec) return HELM_EINVAL;
+    if (w_variant(h)) return HELM_ENOTSUP;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        g_last_error = "hipGetDevice failed";
+        return HELM_EDEVICE;
+    }
+    if (dev != h->device) {
+        g_last_error = "helm_vcycle_noalloc: the current device is not the handle's device";
+        return HELM_EINVAL;
+    }
+    if (dev < 0 || dev >= MAX_SCRATCH_DEVICES) return HELM_ENOTSUP;
+    const Layout Lw = layout_cycle(h, nrhs);
+    if (Lw.total > HELM_NOALLOC_SCRATCH_BYTES) {
+        g_last_error = "helm_vcycle_noalloc: " + std::to_string(nrhs) + " column(s) on this mesh need " +
+                       std::to_string(Lw.total) + " bytes of scratch; the library holds " +
+                       std::to_string((size_t)HELM_NOALLOC_SCRATCH_BYTES) + " per device";
+        return HELM_EINVAL;
+    }
+    // no segment-height timing on this path (it would create events)
+    struct Tuning {
+        bool was;
+        ~Tuning() { (void)stream_tuning(was); }
+    } tuning{stream_tuning(false)};
+    try {
+        void* ws = scratch_on(dev);
+        if (prec == HELM_FP64) vcycle_entry<double>(h, Lw, ws, b, x, nrhs);
+        else vcycle_entry<float>(h, Lw, ws, b, x, nrhs);
+        HIPCHK(hipGetLastError());
     } catch (const DevErr&) {
         return HELM_EDEVICE;
     }

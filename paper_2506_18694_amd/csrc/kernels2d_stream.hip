@@ -671,6 +671,15 @@ struct RowsKey {
 };
 static std::mutex g_rows_mu;
 static std::map<RowsKey, int> g_rows;
+// per-thread switch: when off, a height not measured yet comes from the model
+// (no timing launches, no events created)
+static thread_local bool g_rows_tuning = true;
+
+bool stream_tuning(bool on) {
+    const bool was = g_rows_tuning;
+    g_rows_tuning = on;
+    return was;
+}
 
 // Height for a launch of `kind`; `launch(H)` enqueues the kernel with height
 // H.  tune = false: only look up (the kernel is not safe to repeat).
@@ -683,7 +692,8 @@ static int stream_rows(hipStream_t st, RowsKey key, int halo, bool tune, F launc
     }
     const int model = stream_rows_model(key.n, halo, key.ns);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (!tune || hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    if (!tune || !g_rows_tuning || hipStreamIsCapturing(st, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone)
         return model;
     static const int cand[] = {2, 3, 4, 6, 8, 12, 16, 20, 24, 28, 32, 36, 40, 42, 48, 56, 64, 96, 128};
     hipEvent_t e0 = nullptr, e1 = nullptr;

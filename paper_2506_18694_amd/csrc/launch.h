@@ -67,6 +67,10 @@ template <typename T>
 bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> Xin,
                       Vec<const cx<T>> Ec, Vec<const cx<T>> B, Vec<cx<T>> Xout, Vec<cx<T>> Bc,
                       bool update, int ns);
+// Measuring segment heights on first use (on by default) for the calling
+// thread; returns the previous setting.  Off: heights not measured yet come
+// from the model, and no timing launch or event is made.
+bool stream_tuning(bool on);
 // two zero-guess pre-smoothing sweeps x for L x = b and b_c = P^T (b - L x);
 // b given (B.base set), or b = rho = c (R - B_shift u) (U.base set) or
 // rho = c R (neither), rho then written.

@@ -27,7 +27,7 @@ EXPORTS = ("helm_opts_default", "helm_strerror", "helm_create", "helm_destroy", 
            "helm_vector_length",
            "helm_workspace_bytes", "helm_solve", "helm_load_nodal", "helm_apply",
            "helm_hss_residual", "helm_jacobi", "helm_restrict_residual", "helm_prolong_correct",
-           "helm_coarse_solve", "helm_vcycle", "helm_precondition", "helm_hss_history",
+           "helm_coarse_solve", "helm_vcycle", "helm_vcycle_noalloc", "helm_precondition", "helm_hss_history",
            "helm_last_error",
            "helm_server_create", "helm_server_submit", "helm_server_step", "helm_server_query",
            "helm_server_load", "helm_server_destroy")
@@ -125,6 +125,7 @@ def lib():
         "helm_prolong_correct": (I, [P, I, I, P, P, I]),
         "helm_coarse_solve": (I, [P, I, P, P, I]),
         "helm_vcycle": (I, [P, I, P, P, I, P]),
+        "helm_vcycle_noalloc": (I, [P, I, P, P, I]),
         "helm_precondition": (I, [P, P, P, I, P]),
         "helm_hss_history": (I, [P, P, P, I, P, ctypes.POINTER(D)]),
         "helm_server_create": (I, [ctypes.POINTER(helm_server_opts), ctypes.POINTER(P)]),
@@ -365,6 +366,15 @@ class Solver:
         nrhs = self._cols(b)
         _check(lib().helm_vcycle(self.h, self.prec_code, _ptr(b), _ptr(x), nrhs,
                                  _ptr(self.workspace(nrhs))), "helm_vcycle")
+        return x
+
+    def vcycle_noalloc(self, b, x=None):
+        """The cycle of vcycle() through helm_vcycle_noalloc: the level
+        vectors live in the library's per-device scratch (no workspace)."""
+        if x is None:
+            x = self.torch.empty_like(b)
+        _check(lib().helm_vcycle_noalloc(self.h, self.prec_code, _ptr(b), _ptr(x), self._cols(b)),
+               "helm_vcycle_noalloc")
         return x
 
     def hss_history(self, v):
