@@ -56,15 +56,16 @@ def elapsed():
 # The dominant kernel of each mesh dimension and the source files its
 # counter record depends on.  2D: the finest-level prolongation, four Jacobi
 # sweeps (cycle q's post-smoothing and cycle q+1's pre-smoothing) and the
-# residual restriction in one register-streaming pass.  3D: one
-# finest-level Jacobi sweep, the z-marching column-tile kernel on the
-# interior nodes plus the boundary-node kernel.
+# residual restriction in one register-streaming pass.  3D: the
+# finest-level prolongation and two post-smoothing Jacobi sweeps in one
+# z-marching pass (the cycles before the last of each HSS step).
 DOMINANT = {
     2: {"tag": "k_stream_sweeps4", "sources": ("kernels2d_stream.hip", "helm_common.h", "stencil_rows.h"),
         "desc": "finest-level prolongation + four Jacobi sweeps + residual restriction "
                 "(k_stream_sweeps<S=4>); x, b, e_c read, x', b_c written"},
-    3: {"tag": "k_stencil3d_jacobi", "sources": ("kernels3d.hip", "helm_common.h", "stencil_rows.h"),
-        "desc": "finest-level Jacobi sweep (k_stencil3d_tile + k_stencil3d_bnd); x, b read, x' written"},
+    3: {"tag": "k3_pass_pjac2", "sources": ("kernels3d_fused.hip", "helm_common.h", "launch.h"),
+        "desc": "finest-level prolongation + two Jacobi sweeps (k3_pass<F_JAC, 2, prolong>); "
+                "x, b, e_c read, x' written: 3.125 S N"},
 }
 
 
@@ -284,7 +285,8 @@ def cpu_baseline(W, name, outer_its, cycles, sample_steps, info):
                          if n_s != w["n"] else "", nrhs, workers, t_step, outer_its, hss_steps)}
 
 
-def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1):
+def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1, restart=0,
+                time_cap=None):
     """Continuous-batching run: requests arrive by a seeded Poisson process
     and are submitted when their arrival time passes; the server steps
     continuously.  Latency = completion - arrival (wall clock)."""
@@ -304,7 +306,8 @@ def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1):
     torch.cuda.synchronize()
     for s in loaders.values():
         s.close()
-    srv = Server(hbm_budget_bytes=budget_gb * 1e9, max_cols=max_cols, precision=precision)
+    srv = Server(hbm_budget_bytes=budget_gb * 1e9, max_cols=max_cols, precision=precision,
+                 restart=restart)
     ids, lat, its, conv = {}, {}, [], []
     t0 = time.perf_counter()
     nxt = 0
@@ -316,7 +319,8 @@ def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1):
             r = reqs[nxt]
             ids[nxt], _ = srv.submit(rhs[nxt], r["n"], r["levels"], r["k"], tol=1e-8)
             nxt += 1
-        if not ids:
+        if not ids or (nxt < len(reqs) and sum(srv.load()[:2]) == 0):
+            # nothing queued or running: wait for the next arrival
             time.sleep(max(0.0, reqs[nxt]["arrival"] - now))
             continue
         srv.step()
@@ -337,12 +341,22 @@ def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1):
                         % (done, len(reqs), t, q, run, used / 1e9))
         if nxt == len(reqs) and not ids:
             break
+        if time_cap is not None and time.perf_counter() - t0 > time_cap:
+            log("[serving] time cap reached with %d of %d requests done" % (done, len(reqs)))
+            break
     makespan = time.perf_counter() - t0
     srv.close()
-    L = np.array([lat[i] for i in range(len(reqs))])
-    return {"requests": len(reqs), "sizes": list(sizes), "rate_per_s": rate, "max_cols": max_cols,
+    finished = sorted(lat)
+    L = np.array([lat[i] for i in finished])
+    by_size = {}
+    for i in finished:
+        by_size.setdefault(reqs[i]["n"], []).append(lat[i])
+    return {"requests": len(reqs), "completed": len(finished), "sizes": list(sizes),
+            "rate_per_s": rate, "max_cols": max_cols, "restart": restart,
             "precision": precision, "p50_latency_s": float(np.percentile(L, 50)),
             "p99_latency_s": float(np.percentile(L, 99)), "mean_latency_s": float(L.mean()),
+            "p50_by_size_s": {str(k): float(np.percentile(v, 50)) for k, v in sorted(by_size.items())},
+            "p99_by_size_s": {str(k): float(np.percentile(v, 99)) for k, v in sorted(by_size.items())},
             "makespan_s": makespan, "dofs_per_s": dof / makespan,
             "mean_outer_its": float(np.mean(its)), "all_converged": bool(all(conv))}
 
@@ -524,13 +538,20 @@ def main():
                          "headline workload, no extras")
     ap.add_argument("--serving", action="store_true",
                     help="run the continuous-batching serving workload instead (one JSON line)")
-    ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--sizes", default="128,256,512")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--sizes", default="128,256,512,1024")
     ap.add_argument("--rate", default="auto",
                     help="Poisson arrival rate (requests/s), or 'auto': 0.8 of the capacity "
                          "measured by a saturating batch of requests first")
-    ap.add_argument("--max-cols", type=int, default=16)
-    ap.add_argument("--budget-gb", type=float, default=120.0)
+    ap.add_argument("--max-cols", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--serving-restart", type=int, default=100,
+                    help="FGMRES basis per column in the serving groups")
+    ap.add_argument("--probe-requests", type=int, default=32,
+                    help="size of the saturating batch that measures capacity (rate auto)")
+    ap.add_argument("--time-cap", type=float, default=None,
+                    help="stop the serving run after this many seconds (latencies of the "
+                         "completed requests are reported with the completed count)")
     ap.add_argument("--paper", action="store_true",
                     help="run the paper's own settings (delta_hat = 2, uniform and box sources, "
                          "theta sweep, FGMRES and Richardson) and print their counts and rates")
@@ -589,15 +610,16 @@ def main():
         capacity = None
         if args.rate == "auto":
             # capacity: a batch of requests all queued at t = 0 (another seed)
-            probe = run_serving(W, max(16, args.requests // 4), sizes, None, args.max_cols,
-                                args.budget_gb, "fp32", seed=2)
+            probe = run_serving(W, args.probe_requests, sizes, None, args.max_cols,
+                                args.budget_gb, "fp32", seed=2, restart=args.serving_restart)
             capacity = probe["requests"] / probe["makespan_s"]
             rate = 0.8 * capacity
             log("[serving] capacity %.2f requests/s; offered load 0.8 -> %.2f requests/s"
                 % (capacity, rate))
         else:
             rate = float(args.rate)
-        res = run_serving(W, args.requests, sizes, rate, args.max_cols, args.budget_gb, "fp32")
+        res = run_serving(W, args.requests, sizes, rate, args.max_cols, args.budget_gb, "fp32",
+                          restart=args.serving_restart, time_cap=args.time_cap)
         res["capacity_req_per_s"] = capacity
         res["offered_load"] = rate / capacity if capacity else None
         out = {"metric": "serving p50/p99 latency (continuous batching, FP32-MG/FP64-outer)",
@@ -605,8 +627,9 @@ def main():
                "warmup": 0, "ms_per_step": res["makespan_s"] * 1e3, "higher_is_better": False,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
                "config": {"workload": "serving-2d-p1", **{k: v for k, v in res.items()
-                                                          if k in ("requests", "sizes", "rate_per_s",
-                                                                   "max_cols", "precision",
+                                                          if k in ("requests", "completed", "sizes",
+                                                                   "rate_per_s", "max_cols",
+                                                                   "restart", "precision",
                                                                    "offered_load")}},
                "serving": res}
         print(json.dumps(out), flush=True)

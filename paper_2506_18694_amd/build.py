@@ -19,7 +19,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libhelm.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels2d.hip", "kernels2d_fused.hip", "kernels2d_stream.hip", "kernels2d_small.hip", "kernels3d.hip", "kernels2d_mixed.hip", "kernels_vec.hip", "helm_api.cpp"]
+SOURCES = ["kernels2d.hip", "kernels2d_fused.hip", "kernels2d_stream.hip", "kernels2d_small.hip", "kernels3d.hip", "kernels3d_fused.hip", "kernels2d_mixed.hip", "kernels_vec.hip", "helm_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

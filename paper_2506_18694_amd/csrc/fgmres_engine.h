@@ -152,8 +152,7 @@ struct Engine {
         if (h->dim == 2)
             stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), mode, 1.0, X, Bv, Y, ns);
         else
-            stencil3d<double, double>(s, make_op3<double>(b0, h->n, h->omega), mode, 1.0, X, Bv, Y, ns,
-                                      !h->opts.no_stream);
+            op3d<double, double>(h, s, b0, 0, mode, 1.0, X, Bv, Y, ns);
     }
     void apply_BZ(Vec<const cx<T>> Zv, Vec<cxd> Y, int ns) {
         if (h->mixed) {
@@ -165,8 +164,7 @@ struct Engine {
             stencil2d<double, T>(s, make_op2<double>(b0, h->n, h->omega), MODE_APPLY, 1.0, Zv,
                                  Vec<const cxd>{}, Y, ns);
         else
-            stencil3d<double, T>(s, make_op3<double>(b0, h->n, h->omega), MODE_APPLY, 1.0, Zv,
-                                 Vec<const cxd>{}, Y, ns, !h->opts.no_stream);
+            op3d<double, T>(h, s, b0, 0, MODE_APPLY, 1.0, Zv, Vec<const cxd>{}, Y, ns);
     }
 
     // Enqueue one step's device work.  Returns false if nothing to do.

@@ -150,6 +150,56 @@ Op3<T> make_op3(const Coef& cf, int n, double omega) {
     return o;
 }
 
+// Operator record of the fused 3D passes (kernels3d_fused.hip): the
+// coefficients of the per-plane terms T1, T0 built from the 1D element rows
+// K1 = (1/h)[-1 2 -1], M1 = (h/6)[1 4 1] (boundary rows halve the centre)
+// and the Jacobi factors omega / D by the number of boundary coordinates.
+template <typename T>
+Op3F<T> make_op3f(const Coef& cf, int n, double omega) {
+    const double h = 1.0 / n, h6 = h / 6.0, ih = 1.0 / h;
+    const zd a = cf.a, b = cf.b, c = cf.c;
+    const zd uK = h6 * a, uM = h6 * b - a * ih, uG = h6 * c;
+    const zd vK = 4.0 * h6 * a, vM = 4.0 * h6 * b + 2.0 * a * ih, vG = 4.0 * h6 * c;
+    Op3F<T> o;
+    o.uK = tocx<T>(uK);
+    o.uM = tocx<T>(uM);
+    o.uG = tocx<T>(uG);
+    o.vK = tocx<T>(vK);
+    o.vM = tocx<T>(vM);
+    o.vG = tocx<T>(vG);
+    o.c = tocx<T>(c);
+    // interior columns: PK = (16 a0 - 2 (H + V) - 2 a2) / 6 and
+    // PMM = (h/6)^2 (16 a0 + 4 (H + V) + a2), PG = 0
+    const double pk[3] = {16.0 / 6.0, -2.0 / 6.0, -2.0 / 6.0};
+    const double pm[3] = {16.0 * h6 * h6, 4.0 * h6 * h6, h6 * h6};
+    for (int q = 0; q < 3; ++q) {
+        const zd t1 = uK * pk[q] + uM * pm[q];
+        const zd t0 = vK * pk[q] + vM * pm[q];
+        o.i1[q] = tocx<T>(t1);
+        o.i0[q] = tocx<T>(t0);
+        o.j0[q] = tocx<T>(0.5 * t0 + c * pm[q]);
+    }
+    // diagonal with nb coordinates on the boundary (factors halved there, E = 1)
+    for (int nb = 0; nb < 4; ++nb) {
+        double m[3], k[3], e[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            const bool bnd = ax < nb;
+            m[ax] = bnd ? 2.0 * h6 : 4.0 * h6;
+            k[ax] = bnd ? ih : 2.0 * ih;
+            e[ax] = bnd ? 1.0 : 0.0;
+        }
+        const zd D = a * (k[0] * m[1] * m[2] + m[0] * k[1] * m[2] + m[0] * m[1] * k[2]) +
+                     b * (m[0] * m[1] * m[2]) +
+                     c * (e[0] * m[1] * m[2] + m[0] * e[1] * m[2] + m[0] * m[1] * e[2]);
+        o.od[nb] = tocx<T>(omega / D);
+    }
+    o.h6 = (T)h6;
+    o.ih = (T)ih;
+    o.third = (T)(-1.0 / 3.0);
+    o.n = n;
+    return o;
+}
+
 // In-place inverse of a dense complex matrix by Gauss-Jordan elimination
 // with partial pivoting.  Returns false if singular.
 bool invert_dense(std::vector<zd>& A, int n) {
@@ -361,6 +411,29 @@ Vec<const V> cst(Vec<V> v) {
     return Vec<const V>{v.base, v.cstride, v.off, v.cols};
 }
 
+// 3D levels run the fused z-marching passes (kernels3d_fused.hip) unless
+// switched off (no_stream: one thread per node and the column-tile kernel)
+inline bool fused3d(const helm_t* h) { return h->dim == 3 && !h->opts.no_stream; }
+
+// Op x (MODE_APPLY), s (b - Op x) (MODE_RESID), a Jacobi sweep (MODE_JACOBI)
+// or the zero-guess sweep (MODE_JACOBI0) on 3D level l, for operator cf
+template <typename T, typename TI>
+void op3d(helm_t* h, hipStream_t st, const Coef& cf, int l, int mode, T s, Vec<const cx<TI>> X,
+          Vec<const cx<T>> B, Vec<cx<T>> Y, int ns) {
+    if (fused3d(h) && (mode == MODE_APPLY || mode == MODE_RESID || mode == MODE_JACOBI ||
+                       mode == MODE_JACOBI0)) {
+        const Op3F<T> o = make_op3f<T>(cf, h->nl[l], h->omega);
+        const int first = mode == MODE_APPLY ? F_APPLY
+                          : mode == MODE_RESID ? F_RESID
+                          : mode == MODE_JACOBI ? F_JAC
+                                                : F_PRE0;
+        STREAMCHK((pass3d<T, TI>(st, o, o, first, 1, false, 0, s, X, B, Vec<const cx<T>>{},
+                                 Vec<cx<T>>{}, Y, ns)));
+        return;
+    }
+    stencil3d<T, TI>(st, make_op3<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns, !h->opts.no_stream);
+}
+
 // ---------------------------------------------------------------- levels --
 template <typename T>
 void apply_mode(helm_t* h, int op, int l, int mode, T s, Vec<const cx<T>> X, Vec<const cx<T>> B,
@@ -369,8 +442,7 @@ void apply_mode(helm_t* h, int op, int l, int mode, T s, Vec<const cx<T>> X, Vec
     if (h->dim == 2) {
         stencil2d<T, T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns);
     } else {
-        stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), mode, s, X, B, Y, ns,
-                        !h->opts.no_stream);
+        op3d<T, T>(h, h->stream, cf, l, mode, s, X, B, Y, ns);
     }
 }
 
@@ -380,6 +452,8 @@ void resid_restrict(helm_t* h, int l, Vec<const cx<T>> X, Vec<const cx<T>> B, Ve
     const Coef cf = h->coef(HELM_OP_L);
     if (h->dim == 2) {
         resid_restrict2d<T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
+    } else if (fused3d(h)) {
+        rr3d<T>(h->stream, make_op3f<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
     } else {
         stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), MODE_RESID, (T)1, X, B,
                         tmp, ns, !h->opts.no_stream);
@@ -604,6 +678,87 @@ void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     axpy1<T>(h->stream, N, (T)1, cst(e), u, ns);
 }
 
+// Fused 3D cycle from a zero initial guess on level l: one pass for the two
+// pre-smoothing sweeps (the first from zero), one for the residual
+// restriction, the coarser levels, and one pass for the prolongation and the
+// two post-smoothing sweeps.  b is read, x and t are this level's work
+// buffers; returns the buffer holding the result (x or t).
+template <typename T>
+Vec<cx<T>> vcycle3d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cx<T>> b,
+                         Vec<cx<T>> x, Vec<cx<T>> t, int ns) {
+    if (l == h->levels - 1) {
+        coarse_apply<T>(h->stream, h->d_cinv, h->nc, b, x, ns);
+        return x;
+    }
+    const Op3F<T> L = make_op3f<T>(h->coef(HELM_OP_L), h->nl[l], h->omega);
+    const long long Nc = h->Nl[l + 1];
+    Vec<cx<T>> bc = at_ws<cx<T>>(ws, Lw.mg_b[l + 1], Nc);
+    Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
+    Vec<cx<T>> tc = at_ws<cx<T>>(ws, Lw.mg_t[l + 1], Nc);
+    const Vec<const cx<T>> none{};
+    STREAMCHK((pass3d<T, T>(h->stream, L, L, F_PRE0, 2, false, 0, (T)1, none, b, none, Vec<cx<T>>{}, x, ns)));
+    rr3d<T>(h->stream, L, cst(x), b, bc, ns);
+    Vec<cx<T>> ec = vcycle3d_zero<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
+    STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, true, 0, (T)1, cst(x), b, cst(ec), Vec<cx<T>>{},
+                            t, ns)));
+    return t;
+}
+
+// One shifted-HSS step s with the fused 3D passes: the residual
+// rho = c (R - B_shift u) together with the first cycle's two pre-smoothing
+// sweeps; per cycle the residual restriction, the coarser levels and the
+// prolongation with two post-smoothing sweeps (cycles after the first start
+// with two sweeps from the previous result); the last pass adds its result
+// into u (writes it at step 0, u = 0).
+template <typename T>
+void hss_step3d_fused(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
+    const long long N = h->Nl[0];
+    Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, N);
+    Vec<cx<T>> u = at_ws<cx<T>>(ws, Lw.u, N);
+    Vec<cx<T>> rho = at_ws<cx<T>>(ws, Lw.mg_b[0], N);
+    Vec<cx<T>> x = at_ws<cx<T>>(ws, Lw.mg_x[0], N);
+    Vec<cx<T>> t = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
+    const long long N1 = h->Nl[1];
+    Vec<cx<T>> b1 = at_ws<cx<T>>(ws, Lw.mg_b[1], N1);
+    Vec<cx<T>> x1 = at_ws<cx<T>>(ws, Lw.mg_x[1], N1);
+    Vec<cx<T>> t1 = at_ws<cx<T>>(ws, Lw.mg_t[1], N1);
+    const T c = (T)(2.0 * h->k / (h->k + 1.0));
+    const Op3F<T> L = make_op3f<T>(h->coef(HELM_OP_L), h->nl[0], h->omega);
+    const Op3F<T> Bs = make_op3f<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega);
+    const Vec<const cx<T>> none{};
+    if (s == 0)
+        STREAMCHK((pass3d<T, T>(h->stream, L, Bs, F_HSS0, 2, false, 0, c, none, cst(R), none, rho, x, ns)));
+    else
+        STREAMCHK((pass3d<T, T>(h->stream, L, Bs, F_HSS, 2, false, 0, c, cst(u), cst(R), none, rho, x, ns)));
+    for (int q = 0; q < h->cycles; ++q) {
+        if (q > 0) {
+            STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, false, 0, (T)1, cst(x), cst(rho), none,
+                                    Vec<cx<T>>{}, t, ns)));
+            std::swap(x, t);
+        }
+        rr3d<T>(h->stream, L, cst(x), cst(rho), b1, ns);
+        Vec<const cx<T>> ec = cst(vcycle3d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
+        const bool last = q == h->cycles - 1;
+        // the profiled kernel: the prolongation with two post-smoothing
+        // sweeps of the cycles before the last
+        const bool prof = h->prof_on && !last && s % helm_s::PROF_EVERY == 0;
+        if (prof) h->prof_mark();
+        if (last) {
+            STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, true, s > 0 ? 1 : 0, (T)1, cst(x), cst(rho),
+                                    ec, Vec<cx<T>>{}, u, ns)));
+        } else {
+            STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, true, 0, (T)1, cst(x), cst(rho), ec,
+                                    Vec<cx<T>>{}, t, ns)));
+            std::swap(x, t);
+        }
+        if (prof) {
+            h->prof_mark();
+            // algorithmic bytes: x, rho read, e_c (an eighth vector) read, x' written
+            h->prof_pending_bytes += sizeof(cx<T>) * (double)N * ns * 3.125;
+        }
+    }
+}
+
 // ---- the paper's multigrid variant (Sec. 5.3): W-cycle, GMRES smoothing ----
 #include "wcycle_impl.h"
 
@@ -624,6 +779,7 @@ void hss_step(helm_t* h, const Layout& L, void* ws, int ns, int s) {
         }
     }
     if (h->dim == 2) hss_step2d<T>(h, L, ws, ns, s);
+    else if (fused3d(h) && h->levels > 1) hss_step3d_fused<T>(h, L, ws, ns, s);
     else hss_step3d<T>(h, L, ws, ns, s);
 }
 
@@ -861,8 +1017,9 @@ void vcycle_entry(helm_t* h, const Layout& Lw, void* ws, const void* b, void* x,
             return;
         }
     }
-    if (h->dim == 2) {
-        Vec<cx<T>> r = vcycle2d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns);
+    if (h->dim == 2 || fused3d(h)) {
+        Vec<cx<T>> r = h->dim == 2 ? vcycle2d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns)
+                                   : vcycle3d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns);
         if (r.base != xv.base) copy_cast<T, T>(h->stream, N, cst(r), xv, ns);
     } else {
         vcycle<T>(h, Lw, ws, 0, bv, xv, tv, ns);
@@ -1028,8 +1185,7 @@ int richardson_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, 
             stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), MODE_RESID, 1.0, Xr,
                                       Br, Rr, nr);
         else
-            stencil3d<double, double>(s, make_op3<double>(b0, h->n, h->omega), MODE_RESID, 1.0, Xr,
-                                      Br, Rr, nr, !h->opts.no_stream);
+            op3d<double, double>(h, s, b0, 0, MODE_RESID, 1.0, Xr, Br, Rr, nr);
         norm2(s, N, cst(Rr), d_npart, d_norm, 1, nr);
         HIPCHK(hipMemcpyAsync(hn, d_norm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1147,8 +1303,7 @@ void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>>
             stencil2d<double, T>(s, make_op2<double>(cb, h->n, h->omega), MODE_RESID, 1.0, u, vv, rv,
                                  ns);
         else
-            stencil3d<double, T>(s, make_op3<double>(cb, h->n, h->omega), MODE_RESID, 1.0, u, vv, rv,
-                                 ns, !h->opts.no_stream);
+            op3d<double, T>(h, s, cb, 0, MODE_RESID, 1.0, u, vv, rv, ns);
         norm2(s, N, cst(rv), d_npart, d_norm, 1, ns);
         HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

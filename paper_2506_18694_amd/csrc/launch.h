@@ -111,6 +111,53 @@ void restrict3d(hipStream_t st, int n, Vec<const cx<T>> R, Vec<cx<T>> Bc, int ns
 template <typename T>
 void prolong3d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslots);
 
+// ---- fused z-marching 3D Q1 passes (kernels3d_fused.hip) ------------------
+// Operator record of a K + b M + c M_Gamma on one 3D level for the fused
+// passes: the coefficients of the per-plane terms T1 = uK PK + uM PMM +
+// uG PG and T0 = vK PK + vM PMM + vG PG (uK = (h/6) a, uM = (h/6) b - a/h,
+// uG = (h/6) c, vK = 4 (h/6) a, vM = 4 (h/6) b + 2 a/h, vG = 4 (h/6) c),
+// c for the end planes, and omega / D by the number of coordinates of the
+// node on the mesh boundary (0 interior, 1 face, 2 edge, 3 corner; the
+// diagonal is symmetric in the three axes).
+// Interior columns (no boundary line in x or y) use T1 = i1[0] a0 +
+// i1[1] (H + V) + i1[2] a2 and T0 = i0[.] likewise, and on the first and
+// last plane T0/2 + c PMM = j0[.] likewise.
+template <typename T>
+struct Op3F {
+    cx<T> uK, uM, uG, vK, vM, vG, c;
+    cx<T> i1[3], i0[3], j0[3];
+    cx<T> od[4];
+    T h6, ih, third;  // h / 6, 1 / h, -1/3
+    int n;
+};
+struct Grid3F {
+    int tiles_x, tiles_y, segs, tz;  // tiles per side, plane segments, planes per segment
+};
+// first stage of a fused pass
+enum Pass3First : int {
+    F_APPLY = 0,  // y = L x
+    F_RESID = 1,  // y = s (b - L x)
+    F_JAC = 2,    // x1 = x + w/D (b - L x)   (x + P e_c with the prolongation)
+    F_HSS = 3,    // rho = s (R - B u), x1 = w/D rho
+    F_HSS0 = 4,   // rho = s R, x1 = w/D rho
+    F_PRE0 = 5,   // x1 = w/D b
+};
+// One fused pass: the first stage, and with ns = 2 a Jacobi sweep on its
+// output (b = rho for the HSS forms).  Supported: ns = 1 with F_APPLY,
+// F_RESID, F_JAC, F_PRE0 (any TI); ns = 2 (TI = T) with F_JAC (pro: the
+// input is X + P Ec; upd = 1: Y += result), F_HSS, F_HSS0, F_PRE0.  X, Bv,
+// Ec, Rho, Y as the form needs; Y must not alias X.  tz: planes per
+// segment (0 = from the launch shape).  Returns false (and launches
+// nothing) for an unsupported combination.
+template <typename T, typename TI>
+bool pass3d(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, int first, int ns, bool pro, int upd,
+            T s, Vec<const cx<TI>> X, Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho,
+            Vec<cx<T>> Y, int nslots, int tz = 0);
+// b_c = P^T (b - L x), the n mesh to the n/2 mesh, in one pass
+template <typename T>
+void rr3d(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<cx<T>> Bc,
+          int nslots, int tz = 0);
+
 // ---- mixed [DG0]^2 x P1 formulation (kernels2d_mixed.hip) ------------------
 // X, B, Y of mixed vectors [u | sigma] (sigma after the N = (n+1)^2 nodes).
 // y = sb B_u + Op u + G^T (sa sigma + sg g) at the nodes (B, G nullable; G
