@@ -121,3 +121,37 @@ def test_outer_rate_matches_paper_table_from_random_guess(source):
             rate = (h[-1] / h[0]) ** (1.0 / fi["its"])
             assert abs(rate - (0.2271 if source == "uniform" else 0.2265)) < 0.005, rate
     assert 8 <= its[1.0] <= 10 and 6 <= its[1.5] <= 8 and 29 <= its[0.5] <= 40, its
+
+
+@pytest.mark.parametrize("source,paper_rate", [("uniform", 0.4955), ("box", 0.4960)])
+def test_richardson_rate_matches_paper_in_preconditioned_norm(source, paper_rate):
+    """The paper's measured Richardson rate with exact inner solves at k = 16
+    (its table of Richardson rates: 0.4955 uniform, 0.4960 box) is the mean
+    contraction of the preconditioned residual |B~^{-1}(b - B_0 x_n)| from
+    the paper's random initial guess until it falls below 1e-6 of its
+    initial value: the norm a left-preconditioned Richardson iteration
+    monitors.  The true-residual rate over the same iterations is well below
+    it (about 0.40).
+    The count under this norm is 20 here against the paper's 16 (a reading
+    recorded, not pinned: no stopping reference reproduces both)."""
+    k, n = 16.0, 64
+    pr = solver.Problem(2, n, k, 2.0, levels=1)
+    f = W.uniform_source(2, n) if source == "uniform" else W.box_source(n)
+    b = pr.M @ f
+    x = W.paper_initial_guess(pr.B0.shape[0], 3)
+    P = lambda r: hss.hss_correction(pr.Bdh, r, k, int(np.ceil(k)), pr.solve_L)
+    zs, rs = [], []
+    for _ in range(40):
+        r = b - pr.B0 @ x
+        z = P(r)
+        zs.append(np.linalg.norm(z))
+        rs.append(np.linalg.norm(r))
+        if zs[-1] <= 1e-6 * zs[0]:
+            break
+        x = x + z
+    J = len(zs) - 1
+    rate = (zs[-1] / zs[0]) ** (1.0 / J)
+    assert abs(rate - paper_rate) < 0.01, rate
+    assert 16 <= J <= 22, J
+    true_rate = (rs[-1] / rs[0]) ** (1.0 / J)
+    assert true_rate < rate - 0.05
