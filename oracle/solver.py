@@ -16,6 +16,37 @@ import scipy.sparse.linalg as spla
 from . import fem, operators as ops, hss, multigrid, krylov
 
 
+def nested_dissection_2d(n1, leaf=6):
+    """Nested-dissection order of the n1 x n1 nodes of a 2D mesh (node index
+    i + n1 j).  A box of nodes is split by its middle grid line across the
+    longer side: the two halves are ordered (recursively) first and the
+    line last.  No P1 edge of the right-diagonal triangulation crosses a
+    grid line (edges join nodes at most one row and one column apart), so
+    the two halves of every split are uncoupled in B_0 and their factors
+    fill in only within each half and the separator.  Returns p with
+    p[new] = old."""
+    out = []
+
+    def split(i0, i1, j0, j1):
+        wi, wj = i1 - i0, j1 - j0
+        if wi * wj <= leaf * leaf or min(wi, wj) < 3:
+            I, J = np.meshgrid(np.arange(i0, i1), np.arange(j0, j1), indexing="xy")
+            out.append((I + n1 * J).ravel())
+        elif wi >= wj:
+            m = (i0 + i1) // 2
+            split(i0, m, j0, j1)
+            split(m + 1, i1, j0, j1)
+            out.append(m + n1 * np.arange(j0, j1))
+        else:
+            m = (j0 + j1) // 2
+            split(i0, i1, j0, m)
+            split(i0, i1, m + 1, j1)
+            out.append(np.arange(i0, i1) + n1 * m)
+
+    split(0, n1, 0, n1)
+    return np.concatenate(out)
+
+
 class Problem:
     def __init__(self, dim, n, k, delta_hat, delta=0.0, levels=1, faces=None,
                  nu1=2, nu2=2, omega=2.0 / 3.0, m=1, cycles=2, cycle="v", smooth_its=5):
@@ -45,10 +76,25 @@ class Problem:
         return self._lu_L.solve(np.asarray(r, dtype=np.complex128))
 
     def solve_direct(self, b):
-        """u = B_0^{-1} b by sparse LU."""
+        """u = B_0^{-1} b by sparse LU.  On 2D meshes the unknowns are first
+        put in nested-dissection order (`nested_dissection_2d`), which keeps
+        the factor of a 2049^2-node mesh within a few GB; the solution is
+        the same vector in the original order."""
+        b = np.asarray(b, dtype=np.complex128)
         if self._lu_B0 is None:
-            self._lu_B0 = spla.splu(self.B0.tocsc())
-        return self._lu_B0.solve(np.asarray(b, dtype=np.complex128))
+            if self.dim == 2:
+                p = nested_dissection_2d(self.n + 1)
+                A = self.B0[p][:, p].tocsc()
+                self._lu_B0 = (spla.splu(A, permc_spec="NATURAL", diag_pivot_thresh=0.01,
+                                         options=dict(SymmetricMode=True)), p)
+            else:
+                self._lu_B0 = (spla.splu(self.B0.tocsc()), None)
+        lu, p = self._lu_B0
+        if p is None:
+            return lu.solve(b)
+        u = np.empty_like(b)
+        u[p] = lu.solve(b[p])
+        return u
 
     # -- multigrid ------------------------------------------------------------
     @property

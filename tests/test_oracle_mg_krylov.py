@@ -201,3 +201,34 @@ def test_paper_wcycle_contracts_strongly():
     b = W.random_complex(pr.L.shape[0], 37)
     x = pr.mg_solve(b)
     assert np.linalg.norm(b - pr.L @ x) < 0.01 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("n1", [1, 2, 7, 13, 21, 64])
+def test_nested_dissection_is_a_permutation(n1):
+    p = solver.nested_dissection_2d(n1)
+    assert np.array_equal(np.sort(p), np.arange(n1 * n1))
+
+
+def test_nested_dissection_first_split_decouples_the_halves():
+    """The two halves ordered before the first separator line share no
+    nonzero of B_0 (so the split is a true vertex separator of the P1 mesh)."""
+    n = 20
+    w = solver.Problem(2, n, 5.0, 5.0)
+    n1 = n + 1
+    m = n1 // 2                                      # first split: i = m
+    I = np.arange(n1 * n1) % n1
+    left, right = np.flatnonzero(I < m), np.flatnonzero(I > m)
+    assert abs(w.B0[left][:, right]).max() == 0
+    assert abs(w.B0[left][:, I == m]).max() > 0
+
+
+@pytest.mark.parametrize("n,k", [(7, 3.0), (12, 6.0), (20, 9.0)])
+def test_direct_solve_in_nested_dissection_order_is_the_dense_solve(n, k):
+    """u = B_0^{-1} b through the reordered sparse LU equals numpy's dense
+    LU of the assembled matrix in the original node order."""
+    pr = solver.Problem(2, n, k, k)
+    rng = np.random.default_rng(n)
+    b = rng.standard_normal(pr.B0.shape[0]) + 1j * rng.standard_normal(pr.B0.shape[0])
+    u = pr.solve_direct(b)
+    ud = np.linalg.solve(pr.B0.toarray(), b)
+    assert np.linalg.norm(u - ud) <= 1e-12 * np.linalg.norm(ud)
