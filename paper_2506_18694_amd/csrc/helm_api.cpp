@@ -158,16 +158,10 @@ template <typename T>
 Op3F<T> make_op3f(const Coef& cf, int n, double omega) {
     const double h = 1.0 / n, h6 = h / 6.0, ih = 1.0 / h;
     const zd a = cf.a, b = cf.b, c = cf.c;
+    // T1 = uK PK + uM PMM + uG PG and T0 = vK PK + vM PMM + vG PG
     const zd uK = h6 * a, uM = h6 * b - a * ih, uG = h6 * c;
     const zd vK = 4.0 * h6 * a, vM = 4.0 * h6 * b + 2.0 * a * ih, vG = 4.0 * h6 * c;
     Op3F<T> o;
-    o.uK = tocx<T>(uK);
-    o.uM = tocx<T>(uM);
-    o.uG = tocx<T>(uG);
-    o.vK = tocx<T>(vK);
-    o.vM = tocx<T>(vM);
-    o.vG = tocx<T>(vG);
-    o.c = tocx<T>(c);
     // interior columns: PK = (16 a0 - 2 (H + V) - 2 a2) / 6 and
     // PMM = (h/6)^2 (16 a0 + 4 (H + V) + a2), PG = 0
     const double pk[3] = {16.0 / 6.0, -2.0 / 6.0, -2.0 / 6.0};
@@ -177,7 +171,25 @@ Op3F<T> make_op3f(const Coef& cf, int n, double omega) {
         const zd t0 = vK * pk[q] + vM * pm[q];
         o.i1[q] = tocx<T>(t1);
         o.i0[q] = tocx<T>(t0);
-        o.j0[q] = tocx<T>(0.5 * t0 + c * pm[q]);
+        o.j0[q] = tocx<T>(-0.5 * t0 + c * pm[q]);  // end plane: T0 / 2 + c PMM
+    }
+    // a column on bx + by boundary lines (bx, by in {0, 1}) halves the centre
+    // of the 1D factors in those directions and adds E = 1:
+    //   PMM += (-8 h6^2 nb + 4 h6^2 bx by) a0 - 2 h6^2 w
+    //   PK  += (-8/6 nb + 4/6 bx by) a0 + w / 6
+    //   PG  += (4 h6 nb - 4 h6 bx by) a0 + h6 w
+    // with nb = bx + by and w = bx V + by H; so each of T1, T0 changes by
+    // (A nb + C bx by) a0 + B w with (A, B, C) below, and the end-plane
+    // difference (c PMM - T0 / 2) by c times the PMM change minus half of T0's
+    const double dm[3] = {-8.0 * h6 * h6, -2.0 * h6 * h6, 4.0 * h6 * h6};
+    const double dk[3] = {-8.0 / 6.0, 1.0 / 6.0, 4.0 / 6.0};
+    const double dg[3] = {4.0 * h6, h6, -4.0 * h6};
+    for (int q = 0; q < 3; ++q) {
+        const zd d1 = uK * dk[q] + uM * dm[q] + uG * dg[q];
+        const zd d0 = vK * dk[q] + vM * dm[q] + vG * dg[q];
+        o.e1[q] = tocx<T>(d1);
+        o.e0[q] = tocx<T>(d0);
+        o.f0[q] = tocx<T>(-0.5 * d0 + c * dm[q]);
     }
     // diagonal with nb coordinates on the boundary (factors halved there, E = 1)
     for (int nb = 0; nb < 4; ++nb) {
@@ -193,9 +205,6 @@ Op3F<T> make_op3f(const Coef& cf, int n, double omega) {
                      c * (e[0] * m[1] * m[2] + m[0] * e[1] * m[2] + m[0] * m[1] * e[2]);
         o.od[nb] = tocx<T>(omega / D);
     }
-    o.h6 = (T)h6;
-    o.ih = (T)ih;
-    o.third = (T)(-1.0 / 3.0);
     o.n = n;
     return o;
 }
@@ -678,11 +687,52 @@ void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     axpy1<T>(h->stream, N, (T)1, cst(e), u, ns);
 }
 
-// Fused 3D cycle from a zero initial guess on level l: one pass for the two
-// pre-smoothing sweeps (the first from zero), one for the residual
-// restriction, the coarser levels, and one pass for the prolongation and the
-// two post-smoothing sweeps.  b is read, x and t are this level's work
-// buffers; returns the buffer holding the result (x or t).
+// Two Jacobi sweeps on a 3D level through the fused passes, the first of
+// them replaced as `first` says (the zero-guess sweep, the HSS residual with
+// the zero-guess sweep, or a sweep from X, plus P Ec when pro); the second
+// sweep's right-hand side is rho for the HSS forms, else Bv.  upd = 1 adds
+// the result into Y.  In FP32 one pass runs both sweeps as pipeline stages;
+// in FP64 the two-stage pass does not fit the registers of a 1024-thread
+// workgroup, so two one-stage passes run with T in between.
+// prof: bracket the first launch with timing events (the two-stage pass,
+// or the first one-stage pass) and count its algorithmic bytes per column,
+// `bytes` vectors of the level.
+// The fused 3D sweeps in pairs (two stages per pass) in FP32, one per pass
+// in FP64 (whose two-stage kernels exceed the register budget).
+#ifndef HELM_K3_TWO_STAGE_FP32
+#define HELM_K3_TWO_STAGE_FP32 1
+#endif
+template <typename T>
+constexpr bool two_stage3d() {
+    return sizeof(T) == 4 && HELM_K3_TWO_STAGE_FP32;
+}
+
+template <typename T>
+void sweeps3d(helm_t* h, const Op3F<T>& L, const Op3F<T>& B, int first, bool pro, int upd, T s,
+              Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho,
+              Vec<cx<T>> Tmp, Vec<cx<T>> Y, int ns, bool prof = false, double bytes = 0.0) {
+    const bool two = two_stage3d<T>();
+    if (prof) h->prof_mark();
+    if (two) {
+        STREAMCHK((pass3d<T, T>(h->stream, L, B, first, 2, pro, upd, s, X, Bv, Ec, Rho, Y, ns)));
+    } else {
+        STREAMCHK((pass3d<T, T>(h->stream, L, B, first, 1, pro, 0, s, X, Bv, Ec, Rho, Tmp, ns)));
+    }
+    if (prof) {
+        h->prof_mark();
+        h->prof_pending_bytes += sizeof(cx<T>) * (double)ns * bytes;
+    }
+    if (two) return;
+    const bool hss = first == F_HSS || first == F_HSS0;
+    STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 1, false, upd, (T)1, cst(Tmp), hss ? cst(Rho) : Bv,
+                            Vec<const cx<T>>{}, Vec<cx<T>>{}, Y, ns)));
+}
+
+// Fused 3D cycle from a zero initial guess on level l: the two
+// pre-smoothing sweeps (the first from zero), one pass for the residual
+// restriction, the coarser levels, and the prolongation with the two
+// post-smoothing sweeps.  b is read, x and t are this level's work buffers;
+// returns the buffer holding the result (x or t).
 template <typename T>
 Vec<cx<T>> vcycle3d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const cx<T>> b,
                          Vec<cx<T>> x, Vec<cx<T>> t, int ns) {
@@ -696,19 +746,20 @@ Vec<cx<T>> vcycle3d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const
     Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
     Vec<cx<T>> tc = at_ws<cx<T>>(ws, Lw.mg_t[l + 1], Nc);
     const Vec<const cx<T>> none{};
-    STREAMCHK((pass3d<T, T>(h->stream, L, L, F_PRE0, 2, false, 0, (T)1, none, b, none, Vec<cx<T>>{}, x, ns)));
+    sweeps3d<T>(h, L, L, F_PRE0, false, 0, (T)1, none, b, none, Vec<cx<T>>{}, t, x, ns);
     rr3d<T>(h->stream, L, cst(x), b, bc, ns);
     Vec<cx<T>> ec = vcycle3d_zero<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
-    STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, true, 0, (T)1, cst(x), b, cst(ec), Vec<cx<T>>{},
-                            t, ns)));
-    return t;
+    // the one-stage path ends in x (through t), the two-stage one in t
+    Vec<cx<T>> out = two_stage3d<T>() ? t : x;
+    sweeps3d<T>(h, L, L, F_JAC, true, 0, (T)1, cst(x), b, cst(ec), Vec<cx<T>>{}, t, out, ns);
+    return out;
 }
 
 // One shifted-HSS step s with the fused 3D passes: the residual
 // rho = c (R - B_shift u) together with the first cycle's two pre-smoothing
 // sweeps; per cycle the residual restriction, the coarser levels and the
 // prolongation with two post-smoothing sweeps (cycles after the first start
-// with two sweeps from the previous result); the last pass adds its result
+// with two sweeps from the previous result); the last sweep adds its result
 // into u (writes it at step 0, u = 0).
 template <typename T>
 void hss_step3d_fused(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
@@ -726,35 +777,31 @@ void hss_step3d_fused(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const Op3F<T> L = make_op3f<T>(h->coef(HELM_OP_L), h->nl[0], h->omega);
     const Op3F<T> Bs = make_op3f<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega);
     const Vec<const cx<T>> none{};
-    if (s == 0)
-        STREAMCHK((pass3d<T, T>(h->stream, L, Bs, F_HSS0, 2, false, 0, c, none, cst(R), none, rho, x, ns)));
-    else
-        STREAMCHK((pass3d<T, T>(h->stream, L, Bs, F_HSS, 2, false, 0, c, cst(u), cst(R), none, rho, x, ns)));
+    // the one-stage (FP64) sequence keeps the cycle's iterate in x, with t
+    // between its two sweeps; the two-stage (FP32) one alternates x and t
+    const bool one = !two_stage3d<T>();
+    if (s == 0) sweeps3d<T>(h, L, Bs, F_HSS0, false, 0, c, none, cst(R), none, rho, t, x, ns);
+    else sweeps3d<T>(h, L, Bs, F_HSS, false, 0, c, cst(u), cst(R), none, rho, t, x, ns);
     for (int q = 0; q < h->cycles; ++q) {
         if (q > 0) {
-            STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, false, 0, (T)1, cst(x), cst(rho), none,
-                                    Vec<cx<T>>{}, t, ns)));
-            std::swap(x, t);
+            sweeps3d<T>(h, L, L, F_JAC, false, 0, (T)1, cst(x), cst(rho), none, Vec<cx<T>>{}, t,
+                        one ? x : t, ns);
+            if (!one) std::swap(x, t);
         }
         rr3d<T>(h->stream, L, cst(x), cst(rho), b1, ns);
         Vec<const cx<T>> ec = cst(vcycle3d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
         const bool last = q == h->cycles - 1;
-        // the profiled kernel: the prolongation with two post-smoothing
-        // sweeps of the cycles before the last
+        // the profiled pass: the prolongation with the first (FP64) or both
+        // (FP32) post-smoothing sweeps of the cycles before the last; x, rho
+        // and e_c (an eighth vector) read, the result written
         const bool prof = h->prof_on && !last && s % helm_s::PROF_EVERY == 0;
-        if (prof) h->prof_mark();
         if (last) {
-            STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, true, s > 0 ? 1 : 0, (T)1, cst(x), cst(rho),
-                                    ec, Vec<cx<T>>{}, u, ns)));
+            sweeps3d<T>(h, L, L, F_JAC, true, s > 0 ? 1 : 0, (T)1, cst(x), cst(rho), ec, Vec<cx<T>>{},
+                        t, u, ns);
         } else {
-            STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC, 2, true, 0, (T)1, cst(x), cst(rho), ec,
-                                    Vec<cx<T>>{}, t, ns)));
-            std::swap(x, t);
-        }
-        if (prof) {
-            h->prof_mark();
-            // algorithmic bytes: x, rho read, e_c (an eighth vector) read, x' written
-            h->prof_pending_bytes += sizeof(cx<T>) * (double)N * ns * 3.125;
+            sweeps3d<T>(h, L, L, F_JAC, true, 0, (T)1, cst(x), cst(rho), ec, Vec<cx<T>>{}, t,
+                        one ? x : t, ns, prof, 3.125 * (double)N);
+            if (!one) std::swap(x, t);
         }
     }
 }

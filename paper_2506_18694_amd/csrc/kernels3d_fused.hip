@@ -56,39 +56,77 @@ constexpr int RC = 14;       // coarse columns per tile side in the restriction
 #endif
 constexpr int PF = HELM_K3_PF;  // input planes requested ahead of the one in LDS (>= 1)
 
+// Complex values move as one vector load or store (a struct copy could be
+// split in two, and a select between a load and a local zero turns into a
+// load through a select of addresses, putting the zero in scratch memory).
+template <typename T>
+struct Vec2T;
+template <>
+struct Vec2T<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2T<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+__device__ __forceinline__ cx<T> ldv(const cx<T>* p) {
+    const typename Vec2T<T>::type v = *reinterpret_cast<const typename Vec2T<T>::type*>(p);
+    return mk(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void stv(cx<T>* p, cx<T> a) {
+    typename Vec2T<T>::type v;
+    v.x = a.x;
+    v.y = a.y;
+    *reinterpret_cast<typename Vec2T<T>::type*>(p) = v;
+}
+
+// Selection between two complex values, one component at a time (a select
+// of whole values can be turned into a load through a select of addresses
+// of stack copies).
+template <typename T>
+__device__ __forceinline__ cx<T> csel(bool c, cx<T> a, cx<T> b) {
+    return mk(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+// A value at byte offset off of a plane: the plane's address is the same
+// on every lane (scalar registers), off the lane's column (one 32-bit
+// register), so the loads and stores take the scalar-base form.
+template <typename V>
+__device__ __forceinline__ cx<V> ldo(const cx<V>* plane, unsigned off) {
+    return ldv(reinterpret_cast<const cx<V>*>(reinterpret_cast<const char*>(plane) + off));
+}
+template <typename V>
+__device__ __forceinline__ void sto(cx<V>* plane, unsigned off, cx<V> a) {
+    stv(reinterpret_cast<cx<V>*>(reinterpret_cast<char*>(plane) + off), a);
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> c3(const cx<T>* w, cx<T> a0, cx<T> s1, cx<T> a2) {
     return cfma(w[0], a0, cfma(w[1], s1, w[2] * a2));
 }
 
-// T1, T0 of one plane (see top).  Waves without a column on a boundary
-// line in x or y take the interior coefficients; the others evaluate the
-// factors of each column (bx, by: the column lies on a boundary line; bz:
-// the plane is the first or last).
+// T1, T0 of one plane (see top): the interior coefficients on (a0, H + V,
+// a2), and on waves holding a boundary column the change of the 1D factors
+// there (bx, by: the column lies on a boundary line),
+// (A nb + C bx by) a0 + B (bx V + by H) with nb = bx + by.  On the first and
+// last plane (bz, the same on every lane) T0 becomes T0 / 2 + c PMM: the
+// difference is added in a branch of its own.
 template <typename T>
 __device__ __forceinline__ void plane_terms(const Op3F<T>& op, bool edge_wave, cx<T> a0, cx<T> H,
                                             cx<T> V, cx<T> a2, bool bx, bool by, bool bz, cx<T>& T1,
                                             cx<T>& T0) {
-    if (!edge_wave) {
-        const cx<T> s1 = H + V;
-        T1 = c3(op.i1, a0, s1, a2);
-        T0 = bz ? c3(op.j0, a0, s1, a2) : c3(op.i0, a0, s1, a2);
-        return;
-    }
-    const T h6 = op.h6, ih = op.ih;
-    const T mx = bx ? 2 * h6 : 4 * h6, kx = bx ? ih : 2 * ih;
-    const T my = by ? 2 * h6 : 4 * h6, ky = by ? ih : 2 * ih;
-    const T ex = bx ? (T)1 : (T)0, ey = by ? (T)1 : (T)0;
-    // PMM = mx my a0 + mx h6 V + my h6 H + h6^2 a2
-    const cx<T> pmm = (mx * my) * a0 + (mx * h6) * V + (my * h6) * H + (h6 * h6) * a2;
-    // PK = (kx my + mx ky) a0 + (kx h6 - mx ih) V + (ky h6 - my ih) H - (1/3) a2
-    const cx<T> pk = (kx * my + mx * ky) * a0 + (kx * h6 - mx * ih) * V + (ky * h6 - my * ih) * H +
-                     op.third * a2;
-    // PG = ex (my a0 + h6 V) + ey (mx a0 + h6 H)
-    const cx<T> pg = (ex * my + ey * mx) * a0 + (ex * h6) * V + (ey * h6) * H;
-    T1 = cfma(op.uK, pk, cfma(op.uM, pmm, op.uG * pg));
-    const cx<T> t0 = cfma(op.vK, pk, cfma(op.vM, pmm, op.vG * pg));
-    T0 = bz ? cfma(op.c, pmm, (T)0.5 * t0) : t0;
+    const cx<T> s1 = H + V;
+    T1 = c3(op.i1, a0, s1, a2);
+    T0 = c3(op.i0, a0, s1, a2);
+    if (bz) T0 = T0 + c3(op.j0, a0, s1, a2);
+    if (!edge_wave) return;
+    const T nb = (T)((int)bx + (int)by), bxy = (bx && by) ? (T)1 : (T)0;
+    const cx<T> w = mk((bx ? V.x : (T)0) + (by ? H.x : (T)0), (bx ? V.y : (T)0) + (by ? H.y : (T)0));
+    T1 = cfma(nb * op.e1[0] + bxy * op.e1[2], a0, cfma(op.e1[1], w, T1));
+    T0 = cfma(nb * op.e0[0] + bxy * op.e0[2], a0, cfma(op.e0[1], w, T0));
+    if (bz) T0 = cfma(nb * op.f0[0] + bxy * op.f0[2], a0, cfma(op.f0[1], w, T0));
 }
 
 // in-plane sums at (row r, column q) of an LW x LW LDS plane
@@ -99,21 +137,6 @@ __device__ __forceinline__ void plane_sums(const cx<T> (*pl)[LW], int r, int q, 
     H = pl[r][q - 1] + pl[r][q + 1];
     V = pl[r - 1][q] + pl[r + 1][q];
     a2 = (pl[r - 1][q - 1] + pl[r - 1][q + 1]) + (pl[r + 1][q - 1] + pl[r + 1][q + 1]);
-}
-
-// (P e)(i, j, l), trilinear interpolation from the n/2 mesh: the eight
-// corners of the smallest coarse cell holding the node, with repeats where
-// an offset is even, summed and scaled by 1/8 (exact powers of two)
-template <typename T>
-__device__ __forceinline__ cx<T> prolong_at(const cx<T>* e, int nc, int i, int j, int l) {
-    const long long syc = nc + 1, szc = syc * syc;
-    const long long c0 = (long long)(l >> 1) * szc + (long long)(j >> 1) * syc + (i >> 1);
-    const long long dx = i & 1, dy = (long long)(j & 1) * syc, dz = (long long)(l & 1) * szc;
-    const cx<T> v000 = e[c0], v100 = e[c0 + dx], v010 = e[c0 + dy], v110 = e[c0 + dx + dy];
-    const cx<T> v001 = e[c0 + dz], v101 = e[c0 + dx + dz], v011 = e[c0 + dy + dz],
-                v111 = e[c0 + dx + dy + dz];
-    const cx<T> s = ((v000 + v100) + (v010 + v110)) + ((v001 + v101) + (v011 + v111));
-    return (T)0.125 * s;
 }
 
 // work unit -> (slot, tile x, tile y, segment); the tiles of one segment are
@@ -131,6 +154,24 @@ __device__ __forceinline__ void unit_of(const Grid3F& g, int& slot, int& tx, int
 }
 
 // ---------------------------------------------------------------- k3_pass --
+// The march is unrolled UNR steps at a time so that every ring slot is a
+// fixed register: the load of a plane goes into the slot of the plane that
+// the same step consumed, and no value is moved between slots.  Every load
+// of the unrolled body is issued unconditionally (plane and column indices
+// clamped into the mesh, the value masked where it is consumed), so the
+// count of requests in flight is the same on every path.  (Moving a
+// register whose load is still in flight, or merging paths that issued
+// different numbers of requests, makes the step wait for every request
+// outstanding, and memory returns in order, so it would wait for the
+// prefetches it has just issued.)  UNR is a multiple of the ring depth and
+// of the two LDS buffers; the last partial block runs guarded steps.
+constexpr int UNR = 6;
+static_assert(UNR % PF == 0 && UNR % 2 == 0, "unroll must cover the rings and the LDS buffers");
+constexpr int CW = LW / 2 + 1;  // coarse columns per side under a tile (prolongation)
+
+template <int U>
+using IC = std::integral_constant<int, U>;
+
 // FIRST (the first stage, its output lagging the input by one plane when
 // it is a stencil, in step with it when pointwise):
 //   F_APPLY  y = L x                             (NS = 1)
@@ -142,6 +183,15 @@ __device__ __forceinline__ void unit_of(const Grid3F& g, int& slot, int& tx, int
 //   F_PRE0   x1 = w/D b                          (pointwise)
 // NS = 2 adds x2 = x1 + w/D (b - L x1) (b = rho for the HSS forms).
 // UPD: 0 y = result, 1 y += result (the HSS update u += e with u in Y).
+//
+// Prolongation (PRO): (P e)(i, j, l) is trilinear interpolation from the n/2
+// mesh.  Each coarse plane C the tile needs is staged once in LDS (the
+// CW x CW coarse columns under the tile) and interpolated in-plane to every
+// fine column, ce(C) = sum of the four coarse corners of the column (with
+// repeats where a coordinate is even); a fine plane 2C takes ce(C) / 4 and
+// 2C + 1 takes (ce(C) + ce(C + 1)) / 8 (exact powers of two).  The coarse
+// plane for fine step p is written to LDS one step ahead and requested two
+// steps ahead of that; the march then starts on an even plane.
 template <typename T, typename TI, int FIRST, int NS, bool PRO, int UPD>
 __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<const cx<TI>> X,
                                               Vec<const cx<T>> Bv, Vec<const cx<T>> Ec,
@@ -149,14 +199,17 @@ __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<con
     constexpr bool PW = FIRST == F_HSS0 || FIRST == F_PRE0;
     constexpr bool HSS = FIRST == F_HSS || FIRST == F_HSS0;
     constexpr int OWN = LW - 2 * NS;  // owned columns per tile side
+    static_assert(!(PRO && PW), "the prolongation feeds a stencil first stage");
     __shared__ cx<T> pin[2][LW][LW];
     __shared__ cx<T> pmid[LW][LW];
+    __shared__ cx<T> cpl[PRO ? 2 : 1][PRO ? CW : 1][PRO ? CW : 1];
     int slot, tx, ty, seg;
     unit_of(g, slot, tx, ty, seg);
     const int n = L.n;
     const long long sy = n + 1, sz = sy * sy;
     const int lx = (int)threadIdx.x % LW, ly = (int)threadIdx.x / LW;
-    const int i = tx * OWN - NS + lx, j = ty * OWN - NS + ly;  // this thread's column
+    const int i0 = tx * OWN - NS, j0 = ty * OWN - NS;  // first column of the tile
+    const int i = i0 + lx, j = j0 + ly;                 // this thread's column
     const bool inmesh = (i >= 0) & (i <= n) & (j >= 0) & (j <= n);
     const bool st1 = (lx >= 1) & (lx < LW - 1) & (ly >= 1) & (ly < LW - 1);
     const bool st2 = (lx >= 2) & (lx < LW - 2) & (ly >= 2) & (ly < LW - 2);
@@ -164,66 +217,129 @@ __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<con
     const bool bx = (i == 0) | (i == n), by = (j == 0) | (j == n);
     const bool edge_wave = __any((int)(inmesh & (bx | by)));
     const int cxy = (int)bx + (int)by;  // boundary coordinates in x and y
+    // the Jacobi factor w/D of this column on plane l, indexed by the number
+    // of boundary coordinates (the same on every lane of an interior wave)
+    auto odf = [&](int l) {
+        const bool e = (l == 0) | (l == n);
+        if (!edge_wave) return csel(e, L.od[1], L.od[0]);
+        const int ix = cxy + (int)e;
+        return csel(ix < 2, csel(ix == 0, L.od[0], L.od[1]), csel(ix == 2, L.od[2], L.od[3]));
+    };
     const long long col = inmesh ? (long long)j * sy + i : 0;
+    const unsigned ox = (unsigned)col * (unsigned)sizeof(cx<TI>), ob = (unsigned)col * (unsigned)sizeof(cx<T>);
     const int z0 = seg * g.tz, z1 = min(z0 + g.tz, n + 1);  // output planes [z0, z1)
-    const cx<TI>* x = X.base ? X.at(slot) : nullptr;
-    const cx<T>* bv = Bv.base ? Bv.at(slot) : nullptr;
-    const cx<T>* ec = PRO ? Ec.at(slot) : nullptr;
-    cx<T>* rho = HSS ? Rho.at(slot) : nullptr;
-    cx<T>* y = Y.at(slot);
+    // vector bases (plane l at + l sz)
+    const cx<TI>* xs = X.base ? X.at(slot) : nullptr;
+    const cx<T>* bs = Bv.base ? Bv.at(slot) : nullptr;
+    cx<T>* rs = HSS ? Rho.at(slot) : nullptr;
+    cx<T>* ys = Y.at(slot);
     const cx<T> z = mk((T)0, (T)0);
 
-    // the value this thread stages from input plane p (zero outside the mesh)
-    auto stage = [&](int p) {
-        cx<T> v = z;
-        if (inmesh && p >= 0 && p <= n) {
-            v = cvt<T>(x[(long long)p * sz + col]);
-            if (PRO) v = v + prolong_at<T>(ec, n / 2, i, j, p);
-        }
-        return v;
+    // unconditional loads at this thread's column (column 0 outside the
+    // mesh), plane l clamped into [0, min(hi, n)]; masked where consumed
+    auto pl = [&](int l, int hi) { return (long long)max(0, min(l, min(hi, n))) * sz; };
+    auto ldx = [&](int l, int hi) { return ldo(xs + pl(l, hi), ox); };
+    auto ldcol = [&](const cx<T>* p, int l, int hi) { return ldo(p + pl(l, hi), ob); };
+    auto lok = [&](int l) { return inmesh && l >= 0 && l <= n; };
+    // prolongation: this thread's coarse corner in the tile's LDS coarse
+    // plane, and the coarse value it stages (threads 0 .. CW^2 - 1)
+    const int nc = n / 2;
+    const long long syc = nc + 1, szc = syc * syc;
+    const int cI0 = i0 >> 1, cJ0 = j0 >> 1;  // floor: i0 may be negative
+    const int ci = (i >> 1) - cI0, cj = (j >> 1) - cJ0, cdx = i & 1, cdy = j & 1;
+    const int ca = (int)threadIdx.x % CW, cb = (int)threadIdx.x / CW;
+    const bool cld = PRO && (int)threadIdx.x < CW * CW;
+    const bool cin = cld && cI0 + ca >= 0 && cI0 + ca <= nc && cJ0 + cb >= 0 && cJ0 + cb <= nc;
+    const cx<T>* ecs = PRO ? Ec.at(slot) : nullptr;
+    const unsigned oc = cin ? (unsigned)((cJ0 + cb) * syc + (cI0 + ca)) * (unsigned)sizeof(cx<T>) : 0u;
+    auto ldc = [&](int C) {  // coarse values outside the coarse mesh only reach masked nodes
+        return ldo(ecs + (long long)max(0, min(C, nc)) * szc, oc);
     };
-    auto ldcol = [&](const cx<T>* p, int l) {  // value at this thread's column, plane l
-        return (inmesh && l >= 0 && l <= n) ? p[(long long)l * sz + col] : z;
+    auto interp = [&](int buf) {
+        return (cpl[buf][cj][ci] + cpl[buf][cj][ci + cdx]) +
+               (cpl[buf][cj + cdy][ci] + cpl[buf][cj + cdy][ci + cdx]);
     };
 
     // the first stage outputs planes [o0, o1); a stencil first stage reads
     // input planes [o0 - 1, o1], a pointwise one [o0, o1 - 1]
     const int o0 = z0 - (NS - 1), o1 = z1 + (NS - 1);
-    const int p0 = PW ? o0 : o0 - 1, p1 = PW ? o1 - 1 : o1;
-    cx<T> ring[PF];  // input planes p + 1 .. p + PF (stencil first stage)
-#pragma unroll
-    for (int u = 0; u < PF; ++u) ring[u] = z;
+    int p0 = PW ? o0 : o0 - 1;
+    if (PRO) p0 -= p0 & 1;  // an even first plane (its output is not stored)
+    const int p1 = PW ? o1 - 1 : o1;
+    const int qb = PW ? p0 : p0 - 1;  // plane the first stage outputs at step p0
+    const int qy = NS == 1 ? qb : qb - 1;  // plane the last stage outputs at step p0
+    // rings: x at planes p + 1 .. p + PF, b at q1 .. q1 + PF - 1 and y at the
+    // output planes of steps p .. p + PF - 1 (step p0 + u uses slot u % PF)
+    cx<TI> xr[PF];
+    cx<T> br[PF], yr[PF];
+    cx<T> cA = z, cB = z, cr = z;  // ce of coarse planes C - 1, C; staged coarse value
+    if (PRO) {
+        const int m = p0 >> 1;
+        if (cld) {
+            cpl[m & 1][cb][ca] = ldc(m);
+            cpl[(m + 1) & 1][cb][ca] = ldc(m + 1);
+        }
+        __syncthreads();
+        cB = interp(m & 1);
+        cr = ldc(m + 2);
+    }
     if (!PW) {
-        pin[0][ly][lx] = stage(p0);
+        cx<T> v = cvt<T>(ldx(p0, p1));
+        if (PRO) v = v + (T)0.25 * cB;
+        pin[0][ly][lx] = csel(lok(p0), v, z);
+    }
 #pragma unroll
-        for (int u = 0; u < PF; ++u)
-            if (p0 + 1 + u <= p1) ring[u] = stage(p0 + 1 + u);
+    for (int u = 0; u < PF; ++u) {
+        if (!PW) xr[u] = ldx(p0 + 1 + u, p1);
+        if (FIRST != F_APPLY) br[u] = ldcol(bs, qb + u, o1 - 1);
+        if (UPD == 1) yr[u] = ldcol(ys, qy + u, z1 - 1);
     }
     // stage 1: acc1 = T1(q - 1) + T0(q) for the next output plane q, T1p = T1(q);
     // xc: input centre of q.  Stage 2 likewise, with b2 its right-hand side.
     cx<T> acc1 = z, T1p = z, xc = z;
-    cx<T> acc2 = z, U1p = z, xc2 = z, b2 = z, bq = z;
-    cx<T> bnext = FIRST != F_APPLY ? ldcol(bv, PW ? p0 : p0 - 1) : z;
-    int k = 0;
-    for (int p = p0; p <= p1; ++p) {
+    cx<T> acc2 = z, U1p = z, xc2 = z, b2 = z;
+
+    auto step = [&](auto uc, int p) __attribute__((always_inline)) {
+        constexpr int u = decltype(uc)::value;
+        constexpr int kb = u & 1;   // LDS buffer of input plane p
+        constexpr int sl = u % PF;  // ring slot of this step
         const int q1 = PW ? p : p - 1;  // plane the first stage outputs at this step
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
-        cx<T> vn = z;
-        if (!PW && p + PF + 1 <= p1) vn = stage(p + PF + 1);
-        const cx<T> bcur = bnext;
-        if (FIRST != F_APPLY && q1 + 1 < o1) bnext = ldcol(bv, q1 + 1);
+        if (!PW) {
+            // input plane p + 1 into the buffer of plane p - 1 (free since the
+            // barrier; past the last plane it is written and never read)
+            cx<T> v = cvt<T>(xr[sl]);
+            if (PRO) {
+                if (kb == 0) {  // p + 1 = 2C - 1
+                    cA = cB;
+                    cB = interp(((p + 2) >> 1) & 1);
+                    v = v + (T)0.125 * (cA + cB);
+                } else {  // p + 1 = 2C
+                    v = v + (T)0.25 * cB;
+                }
+            }
+            pin[kb ^ 1][ly][lx] = csel(lok(p + 1), v, z);
+            xr[sl] = ldx(p + 1 + PF, p1);
+            if (PRO && kb == 1) {  // coarse plane (p + 3) / 2, needed at step p + 1
+                if (cld) cpl[((p + 3) >> 1) & 1][cb][ca] = cr;
+                cr = ldc((p + 5) >> 1);
+            }
+        }
+        const cx<T> bcur = br[sl];
+        if (FIRST != F_APPLY) br[sl] = ldcol(bs, q1 + PF, o1 - 1);
         const bool q1ok = inmesh && q1 >= 0 && q1 <= n && q1 >= o0;
-        const int cls = cxy + (int)((q1 == 0) | (q1 == n));
-        cx<T> x1 = z;
+        const cx<T> od1 = odf(q1);
+        cx<T> x1 = z, bq = z;
         if (PW) {
             if (q1ok) {
                 if (FIRST == F_HSS0) {
                     const cx<T> r = s * bcur;
-                    if (owned && q1 >= z0 && q1 < z1) rho[(long long)q1 * sz + col] = r;
-                    x1 = L.od[cls] * r;
+                    if (owned && q1 >= z0 && q1 < z1) sto(rs + (long long)q1 * sz, ob, r);
+                    x1 = od1 * r;
                     bq = r;
                 } else {
-                    x1 = L.od[cls] * bcur;
+                    x1 = od1 * bcur;
                     bq = bcur;
                 }
             }
@@ -232,7 +348,7 @@ __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<con
             cx<T> t1 = z, t0 = z, a0 = z;
             if (st1) {
                 cx<T> H, V, a2;
-                plane_sums<T>(pin[k], ly, lx, a0, H, V, a2);
+                plane_sums<T>(pin[kb], ly, lx, a0, H, V, a2);
                 plane_terms<T>(A, edge_wave, a0, H, V, a2, bx, by, (p == 0) | (p == n), t1, t0);
                 if (p < 0 || p > n) t1 = t0 = z;
             }
@@ -243,52 +359,68 @@ __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<con
                 } else if (FIRST == F_RESID) {
                     x1 = s * (bcur - ax);
                 } else if (FIRST == F_JAC) {
-                    x1 = cfma(L.od[cls], bcur - ax, xc);
+                    x1 = cfma(od1, bcur - ax, xc);
                     bq = bcur;
                 } else {  // F_HSS
                     const cx<T> r = s * (bcur - ax);
-                    if (owned && q1 >= z0 && q1 < z1) rho[(long long)q1 * sz + col] = r;
-                    x1 = L.od[cls] * r;
+                    if (owned && q1 >= z0 && q1 < z1) sto(rs + (long long)q1 * sz, ob, r);
+                    x1 = od1 * r;
                     bq = r;
                 }
             }
             acc1 = T1p + t0;
             T1p = t1;
             xc = a0;
-            if (p + 1 <= p1) pin[k ^ 1][ly][lx] = ring[0];
-#pragma unroll
-            for (int u = 0; u + 1 < PF; ++u) ring[u] = ring[u + 1];
-            ring[PF - 1] = vn;
-            k ^= 1;
         }
         if (NS == 1) {
-            if (owned && q1ok && q1 < z1) {
-                const long long t = (long long)q1 * sz + col;
-                y[t] = UPD == 1 ? y[t] + x1 : x1;
+            if (UPD == 1) {
+                const cx<T> yo = yr[sl];
+                yr[sl] = ldcol(ys, q1 + PF, z1 - 1);
+                if (owned && q1ok && q1 < z1) sto(ys + (long long)q1 * sz, ob, yo + x1);
+            } else if (owned && q1ok && q1 < z1) {
+                sto(ys + (long long)q1 * sz, ob, x1);
             }
-            continue;
+            return;
         }
         // second stage: x1 of plane q1 through the middle plane; output q1 - 1
         pmid[ly][lx] = x1;
         __syncthreads();
+        const int q2 = q1 - 1;
+        cx<T> yo = z;
+        if (UPD == 1) {
+            yo = yr[sl];
+            yr[sl] = ldcol(ys, q2 + PF, z1 - 1);
+        }
         if (st2) {
             cx<T> a0, H, V, a2, u1 = z, u0 = z;
             plane_sums<T>(pmid, ly, lx, a0, H, V, a2);
             if (q1 >= 0 && q1 <= n)
                 plane_terms<T>(L, edge_wave, a0, H, V, a2, bx, by, (q1 == 0) | (q1 == n), u1, u0);
-            const int q2 = q1 - 1;
             if (owned && q2 >= z0 && q2 < z1) {
-                const int cls2 = cxy + (int)((q2 == 0) | (q2 == n));
-                const cx<T> x2 = cfma(L.od[cls2], b2 - (acc2 + u1), xc2);
-                const long long t = (long long)q2 * sz + col;
-                y[t] = UPD == 1 ? y[t] + x2 : x2;
+                const cx<T> od2 = odf(q2);
+                const cx<T> x2 = cfma(od2, b2 - (acc2 + u1), xc2);
+                sto(ys + (long long)q2 * sz, ob, UPD == 1 ? yo + x2 : x2);
             }
             acc2 = U1p + u0;
             U1p = u1;
             xc2 = a0;
             b2 = bq;
         }
+    };
+    int pb = p0;
+    for (; pb + UNR - 1 <= p1; pb += UNR) {
+        step(IC<0>{}, pb);
+        step(IC<1>{}, pb + 1);
+        step(IC<2>{}, pb + 2);
+        step(IC<3>{}, pb + 3);
+        step(IC<4>{}, pb + 4);
+        step(IC<5>{}, pb + 5);
     }
+    if (pb <= p1) step(IC<0>{}, pb);
+    if (pb + 1 <= p1) step(IC<1>{}, pb + 1);
+    if (pb + 2 <= p1) step(IC<2>{}, pb + 2);
+    if (pb + 3 <= p1) step(IC<3>{}, pb + 3);
+    if (pb + 4 <= p1) step(IC<4>{}, pb + 4);
 }
 
 // ------------------------------------------------------------------ k3_rr --
@@ -297,7 +429,8 @@ __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<con
 // 2 I - 1 .. 2 I + 1 around them, the second stage restricts each residual
 // plane in-plane on the coarse columns and accumulates it into the coarse
 // planes (weight 1 on plane 2 L, 1/2 on 2 L +- 1).  Segments own coarse
-// planes [Z0, Z0 + tz).
+// planes [Z0, Z0 + tz).  The march starts on an even plane and is unrolled
+// as in k3_pass.
 template <typename T>
 __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<const cx<T>> Bv,
                                             Vec<cx<T>> Bc, Grid3F g) {
@@ -316,9 +449,10 @@ __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<c
     const bool bx = (i == 0) | (i == n), by = (j == 0) | (j == n);
     const bool edge_wave = __any((int)(inmesh & (bx | by)));
     const long long col = inmesh ? (long long)j * sy + i : 0;
+    const unsigned ob = (unsigned)col * (unsigned)sizeof(cx<T>);
     const int Z0 = seg * g.tz, Z1 = min(Z0 + g.tz, nc + 1);
-    const cx<T>* x = X.at(slot);
-    const cx<T>* bv = Bv.at(slot);
+    const cx<T>* xs = X.at(slot);
+    const cx<T>* bs = Bv.at(slot);
     cx<T>* bc = Bc.at(slot);
     const cx<T> z = mk((T)0, (T)0);
     // coarse column of the second stage (threads 0 .. RC^2 - 1); its fine
@@ -327,33 +461,43 @@ __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<c
     const int ci = (int)threadIdx.x % RC, cj = (int)threadIdx.x / RC;
     const int I = RC * tx + ci, J = RC * ty + cj;
     const bool cown = cst & (I <= nc) & (J <= nc);
-    const long long ccol = cown ? (long long)J * syc + I : 0;
+    const unsigned occ = cown ? (unsigned)(J * syc + I) * (unsigned)sizeof(cx<T>) : 0u;
 
-    auto stage = [&](int p) {
-        return (inmesh && p >= 0 && p <= n) ? x[(long long)p * sz + col] : z;
+    // unconditional loads (see k3_pass), masked where consumed
+    auto ldcol = [&](const cx<T>* p, int l, int hi) {
+        return ldo(p + (long long)max(0, min(l, min(hi, n))) * sz, ob);
     };
-    auto ldb = [&](int l) { return (inmesh && l >= 0 && l <= n) ? bv[(long long)l * sz + col] : z; };
+    auto lok = [&](int l) { return inmesh && l >= 0 && l <= n; };
     // residual planes [2 Z0 - 1, 2 Z1 - 1] are formed at steps p = q + 1;
-    // the input starts one plane below the first of them
+    // the input starts one plane below the first of them (p0 is even)
     const int p0 = 2 * Z0 - 2, p1 = 2 * Z1;
-    pin[0][ly][lx] = stage(p0);
-    cx<T> ring[PF];
+    {
+        const cx<T> v = ldcol(xs, p0, p1);
+        pin[0][ly][lx] = csel(lok(p0), v, z);
+    }
+    cx<T> xr[PF], br[PF];  // x at planes p + 1 .. p + PF; b at q .. q + PF - 1
 #pragma unroll
-    for (int u = 0; u < PF; ++u) ring[u] = p0 + 1 + u <= p1 ? stage(p0 + 1 + u) : z;
-    cx<T> acc = z, T1p = z, bnext = ldb(p0 - 1);
+    for (int u = 0; u < PF; ++u) {
+        xr[u] = ldcol(xs, p0 + 1 + u, p1);
+        br[u] = ldcol(bs, p0 - 1 + u, p1 - 1);
+    }
+    cx<T> acc = z, T1p = z;
     cx<T> cur = z, half = z;  // coarse accumulators of the second stage
-    int k = 0;
-    for (int p = p0; p <= p1; ++p) {
-        const int q = p - 1;  // residual plane formed at this step
+
+    auto step = [&](auto uc, int p) __attribute__((always_inline)) {
+        constexpr int u = decltype(uc)::value;
+        constexpr int kb = u & 1;
+        constexpr int sl = u % PF;
+        const int q = p - 1;  // residual plane formed at this step (odd when u is even)
         __syncthreads();
-        cx<T> vn = z;
-        if (p + PF + 1 <= p1) vn = stage(p + PF + 1);
-        const cx<T> bcur = bnext;
-        bnext = ldb(q + 1);
+        pin[kb ^ 1][ly][lx] = csel(lok(p + 1), xr[sl], z);
+        xr[sl] = ldcol(xs, p + 1 + PF, p1);
+        const cx<T> bcur = br[sl];
+        br[sl] = ldcol(bs, q + PF, p1 - 1);
         cx<T> t1 = z, t0 = z;
         if (st1) {
             cx<T> a0, H, V, a2;
-            plane_sums<T>(pin[k], ly, lx, a0, H, V, a2);
+            plane_sums<T>(pin[kb], ly, lx, a0, H, V, a2);
             plane_terms<T>(L, edge_wave, a0, H, V, a2, bx, by, (p == 0) | (p == n), t1, t0);
             if (p < 0 || p > n) t1 = t0 = z;
         }
@@ -361,38 +505,62 @@ __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<c
         if (st1 && inmesh && q >= 0 && q <= n) r = bcur - (acc + t1);
         acc = T1p + t0;
         T1p = t1;
-        if (p + 1 <= p1) pin[k ^ 1][ly][lx] = ring[0];
-#pragma unroll
-        for (int u = 0; u + 1 < PF; ++u) ring[u] = ring[u + 1];
-        ring[PF - 1] = vn;
-        k ^= 1;
         pres[ly][lx] = r;
         __syncthreads();
         if (cst) {
             cx<T> c0, cH, cV, c2;
             plane_sums<T>(pres, 2 * cj + 2, 2 * ci + 2, c0, cH, cV, c2);
             const cx<T> r2 = c0 + (T)0.5 * (cH + cV) + (T)0.25 * c2;
-            if (q & 1) {
+            if (kb == 0) {  // q odd
                 const int Lc = (q - 1) >> 1;  // coarse plane completed by this odd plane
-                if (cown && Lc >= Z0 && Lc < Z1) bc[(long long)Lc * szc + ccol] = cur + (T)0.5 * r2;
+                if (cown && Lc >= Z0 && Lc < Z1) sto(bc + (long long)Lc * szc, occ, cur + (T)0.5 * r2);
                 half = (T)0.5 * r2;
             } else {
                 cur = half + r2;
             }
         }
+    };
+    int pb = p0;
+    for (; pb + UNR - 1 <= p1; pb += UNR) {
+        step(IC<0>{}, pb);
+        step(IC<1>{}, pb + 1);
+        step(IC<2>{}, pb + 2);
+        step(IC<3>{}, pb + 3);
+        step(IC<4>{}, pb + 4);
+        step(IC<5>{}, pb + 5);
     }
+    if (pb <= p1) step(IC<0>{}, pb);
+    if (pb + 1 <= p1) step(IC<1>{}, pb + 1);
+    if (pb + 2 <= p1) step(IC<2>{}, pb + 2);
+    if (pb + 3 <= p1) step(IC<3>{}, pb + 3);
+    if (pb + 4 <= p1) step(IC<4>{}, pb + 4);
 }
 
-// Segment height: output planes per workgroup.  One 1024-thread workgroup
-// runs per CU, so a launch takes ceil(units / 256) rounds, each as long as
-// one segment's march (its planes plus a pipeline head of about four); the
-// height minimises rounds x (planes + 4), at least 8 planes unless one
-// segment covers the level.
-int seg_planes(int planes, int tiles, int nslots) {
+// Workgroups of a kernel that the device holds at once (its occupancy per
+// CU, from its register and LDS use, times the CUs), asked once per kernel.
+template <auto K>
+int resident_units() {
+    static const int units = [] {
+        int nb = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, K, FT, 0) != hipSuccess || nb < 1) nb = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        return nb * cus;
+    }();
+    return units;
+}
+
+// Segment height: output planes per workgroup.  A launch takes
+// ceil(units / resident) rounds, each as long as one segment's march (its
+// planes plus a pipeline head of about four); the height minimises
+// rounds x (planes + 4), at least 8 planes unless one segment covers the
+// level.
+int seg_planes(int planes, int tiles, int nslots, int resident) {
 #ifdef HELM_K3_SEGS
     return (planes + HELM_K3_SEGS - 1) / HELM_K3_SEGS;
 #endif
-    const long long cus = 256;
+    const long long cus = resident;
     int best = planes;
     long long best_cost = -1;
     for (int segs = 1; segs <= planes; ++segs) {
@@ -409,24 +577,32 @@ int seg_planes(int planes, int tiles, int nslots) {
     return best;
 }
 
+template <typename T, typename TI, int F, int NS, bool PRO, int UPD>
+void launch_pass(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
+                 Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
+                 int tz) {
+    const int n = L.n, own = LW - 2 * NS;
+    Grid3F g;
+    g.tiles_x = (n + 1 + own - 1) / own;
+    g.tiles_y = g.tiles_x;
+    g.tz = tz > 0 ? tz
+                  : seg_planes(n + 1, g.tiles_x * g.tiles_y, nslots,
+                               resident_units<k3_pass<T, TI, F, NS, PRO, UPD>>());
+    g.segs = (n + 1 + g.tz - 1) / g.tz;
+    const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
+    k3_pass<T, TI, F, NS, PRO, UPD><<<grid, FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g);
+}
+
 }  // namespace
 
 template <typename T, typename TI>
 bool pass3d(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, int first, int ns, bool pro, int upd,
             T s, Vec<const cx<TI>> X, Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho,
             Vec<cx<T>> Y, int nslots, int tz) {
-    const int n = L.n;
-    const int own = LW - 2 * ns;
-    Grid3F g;
-    g.tiles_x = (n + 1 + own - 1) / own;
-    g.tiles_y = (n + 1 + own - 1) / own;
-    g.tz = tz > 0 ? tz : seg_planes(n + 1, g.tiles_x * g.tiles_y, nslots);
-    g.segs = (n + 1 + g.tz - 1) / g.tz;
-    const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
-#define HELM_P3(F, NS_, PRO_, UPD_)                                                               \
-    do {                                                                                          \
-        k3_pass<T, TI, F, NS_, PRO_, UPD_><<<grid, FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g); \
-        return true;                                                                              \
+#define HELM_P3(F, NS_, PRO_, UPD_)                                                              \
+    do {                                                                                         \
+        launch_pass<T, TI, F, NS_, PRO_, UPD_>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);     \
+        return true;                                                                             \
     } while (0)
     if (ns == 1 && !pro && upd == 0) {
         if (first == F_APPLY) HELM_P3(F_APPLY, 1, false, 0);
@@ -435,6 +611,12 @@ bool pass3d(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, int first, int n
         if (first == F_PRE0) HELM_P3(F_PRE0, 1, false, 0);
     }
     if constexpr (std::is_same<T, TI>::value) {
+        if (ns == 1) {
+            if (first == F_JAC && pro && upd == 0) HELM_P3(F_JAC, 1, true, 0);
+            if (first == F_JAC && !pro && upd == 1) HELM_P3(F_JAC, 1, false, 1);
+            if (first == F_HSS && !pro && upd == 0) HELM_P3(F_HSS, 1, false, 0);
+            if (first == F_HSS0 && !pro && upd == 0) HELM_P3(F_HSS0, 1, false, 0);
+        }
         if (ns == 2) {
             if (first == F_JAC && !pro && upd == 0) HELM_P3(F_JAC, 2, false, 0);
             if (first == F_JAC && pro && upd == 0) HELM_P3(F_JAC, 2, true, 0);
@@ -455,7 +637,9 @@ void rr3d(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>>
     Grid3F g;
     g.tiles_x = (nc + 1 + RC - 1) / RC;
     g.tiles_y = g.tiles_x;
-    g.tz = tz > 0 ? tz : std::max(4, seg_planes(2 * nc + 1, g.tiles_x * g.tiles_y, nslots) / 2);
+    g.tz = tz > 0 ? tz
+                  : std::max(4, seg_planes(2 * nc + 1, g.tiles_x * g.tiles_y, nslots,
+                                           resident_units<k3_rr<T>>()) / 2);
     g.segs = (nc + 1 + g.tz - 1) / g.tz;
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
     k3_rr<T><<<grid, FT, 0, st>>>(L, X, Bv, Bc, g);

@@ -124,10 +124,9 @@ void prolong3d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslo
 // last plane T0/2 + c PMM = j0[.] likewise.
 template <typename T>
 struct Op3F {
-    cx<T> uK, uM, uG, vK, vM, vG, c;
-    cx<T> i1[3], i0[3], j0[3];
+    cx<T> i1[3], i0[3], j0[3];  // T1, T0, and T0 of an end plane minus T0, on interior columns
+    cx<T> e1[3], e0[3], f0[3];  // their changes on a boundary column (see kernels3d_fused.hip)
     cx<T> od[4];
-    T h6, ih, third;  // h / 6, 1 / h, -1/3
     int n;
 };
 struct Grid3F {
@@ -144,8 +143,9 @@ enum Pass3First : int {
 };
 // One fused pass: the first stage, and with ns = 2 a Jacobi sweep on its
 // output (b = rho for the HSS forms).  Supported: ns = 1 with F_APPLY,
-// F_RESID, F_JAC, F_PRE0 (any TI); ns = 2 (TI = T) with F_JAC (pro: the
-// input is X + P Ec; upd = 1: Y += result), F_HSS, F_HSS0, F_PRE0.  X, Bv,
+// F_RESID, F_JAC, F_PRE0 (any TI), and (TI = T) F_JAC with pro (the input
+// is X + P Ec) or upd = 1 (Y += result), F_HSS, F_HSS0; ns = 2 (TI = T)
+// with F_JAC (pro, upd as before), F_HSS, F_HSS0, F_PRE0.  X, Bv,
 // Ec, Rho, Y as the form needs; Y must not alias X.  tz: planes per
 // segment (0 = from the launch shape).  Returns false (and launches
 // nothing) for an unsupported combination.
