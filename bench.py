@@ -14,8 +14,8 @@ solved with FP32 multigrid and FP64 outer iteration (`fp32_mg`, with the
 FP64/FP32-MG DoF/s ratio), and the 2D P1 configurations 64^2 (k = 10),
 1024^2 (k = 100, four right-hand sides) and 2048^2 (k = 200) are reported
 in `workloads`, each in both precision modes with its error against the
-oracle's direct solve where the oracle can factorise the mesh (64^2 in
-process, 1024^2 in a CPU worker process that runs beside the GPU work).
+oracle's direct solve (64^2 in process; 1024^2 and 2048^2 in CPU worker
+processes that run beside the GPU work).
 
 --steps and --warmup are caps: the run plans its solves against a
 wall-clock budget (--budget-s, measured from process start, default 450 s)
@@ -57,14 +57,16 @@ def elapsed():
 # counter record depends on.  2D: the finest-level prolongation, four Jacobi
 # sweeps (cycle q's post-smoothing and cycle q+1's pre-smoothing) and the
 # residual restriction in one register-streaming pass.  3D: the
-# finest-level prolongation and two post-smoothing Jacobi sweeps in one
-# z-marching pass (the cycles before the last of each HSS step).
+# finest-level prolongation and the post-smoothing Jacobi sweep(s) of one
+# z-marching pass (one sweep in FP64, two in FP32; the cycles before the
+# last of each HSS step).
 DOMINANT = {
     2: {"tag": "k_stream_sweeps4", "sources": ("kernels2d_stream.hip", "helm_common.h", "stencil_rows.h"),
         "desc": "finest-level prolongation + four Jacobi sweeps + residual restriction "
                 "(k_stream_sweeps<S=4>); x, b, e_c read, x', b_c written"},
-    3: {"tag": "k3_pass_pjac2", "sources": ("kernels3d_fused.hip", "helm_common.h", "launch.h"),
-        "desc": "finest-level prolongation + two Jacobi sweeps (k3_pass<F_JAC, 2, prolong>); "
+    3: {"tag": "k3_pass_prolong", "sources": ("kernels3d_fused.hip", "helm_common.h", "launch.h"),
+        "desc": "finest-level prolongation + Jacobi sweep(s) in one z-marching pass "
+                "(k3_pass<F_JAC, stages, prolong>: one sweep in FP64, two in FP32); "
                 "x, b, e_c read, x' written: 3.125 S N"},
 }
 
@@ -658,11 +660,14 @@ def main():
     head_prec = args.precision
     other = [] if args.only_headline else [n for n in ("p1-64-k10", "p1-1024-k100", "p1-2048-k200")
                                            if n != args.workload]
-    # the 1024^2 direct solve (about a minute of one core) runs beside the GPU work
-    worker = None
-    if "p1-1024-k100" in other and not args.no_oracle_error:
-        worker = start_oracle_worker("p1-1024-k100", tmpdir)
-        log("[bench] oracle direct-solve worker started for p1-1024-k100")
+    # the oracle's direct solves of the 1024^2 and 2048^2 meshes (sparse LU in
+    # nested-dissection order: ~15 s and ~1.5 min) run beside the GPU work
+    workers = {}
+    if not args.no_oracle_error:
+        for name in other:
+            if name in ("p1-1024-k100", "p1-2048-k200"):
+                workers[name] = start_oracle_worker(name, tmpdir)
+                log("[bench] oracle direct-solve worker started for %s" % name)
     # time the rest of the run needs after the headline's FP64 solves, in
     # units of one headline solve (FP32-MG: a cheaper solve, no full warm-up)
     # plus the fixed-size parts (2D configurations, CPU baseline, margin)
@@ -734,8 +739,8 @@ def main():
                 pr = osolver.Problem(2, w["n"], w["k"], w["delta_hat"], levels=1)
                 U = np.stack([pr.solve_direct((pr.M @ fi).astype(np.complex128))
                               for fi in W.workload_sources(name)])
-            elif worker is not None and name == "p1-1024-k100":
-                p, path = worker
+            elif name in workers:
+                p, path = workers[name]
                 p.join(timeout=max(1.0, budget - elapsed() - fixed_rest))
                 if os.path.exists(path):
                     U = np.load(path)
@@ -749,8 +754,9 @@ def main():
             % (name, ent["fp64"]["value"], ent["fp32_mg"]["value"], ent["ratio_fp32mg_vs_fp64"]))
     if subs:
         out["workloads"] = subs
-    if worker is not None and worker[0].is_alive():
-        worker[0].terminate()
+    for p, _ in workers.values():
+        if p.is_alive():
+            p.terminate()
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline sample ...")
         out["cpu_baseline"] = cpu_baseline(W, args.workload, out["config"]["outer_its"],

@@ -160,7 +160,12 @@ def test_2048_apply_sampled(prec, tol):
     s.close()
 
 
+@pytest.mark.timeout(900)
 def test_2048_fp32_solve_residual():
+    """The 2048^2, k = 200 solve with FP32 multigrid: converged to 1e-8, the
+    true residual through the FP64 apply, sampled rows of that apply against
+    the oracle's element matrices, and the relative l2 error against the
+    oracle's FP64 sparse direct solution (<= 1e-5; printed)."""
     import torch
     name = "p1-2048-k200"
     w = W.WORKLOADS[name]
@@ -179,6 +184,17 @@ def test_2048_fp32_solve_residual():
     assert _sampled_2d(w["n"], w["k"], xh, y, 51) < 1e-10
     s.close()
     s64.close()
+    del b, x, y, f
+    torch.cuda.empty_cache()
+    # the oracle's direct solve (nested-dissection sparse LU, ~1-2 min)
+    pr = osolver.Problem(2, w["n"], w["k"], w["delta_hat"], levels=1)
+    fh = W.workload_sources(name)[0]
+    assert rel_l2(bh, pr.M @ fh) < 1e-12
+    u = pr.solve_direct(pr.M @ fh.astype(np.complex128))
+    assert np.linalg.norm(pr.M @ fh - pr.B0 @ u) <= 1e-10 * np.linalg.norm(pr.M @ fh)
+    err = rel_l2(xh, u)
+    print("p1-2048-k200 fp32-mg rel l2 error vs oracle direct: %.3e" % err)
+    assert err <= 1e-5
 
 
 def test_headline_fp32_mg_runs_in_fp32(head):
