@@ -389,15 +389,21 @@ int helm_hss_history(helm_t* h, const void* v, void* z, int nrhs, void* workspac
  * A server solves a stream of requests (one mesh, k, delta_hat and a set of
  * right-hand sides each).  Requests with the same mesh and parameters form a
  * group that shares one solver handle, one device workspace of `max_cols`
- * column slots and one stream; every column owns a slot (its own Krylov
- * basis and iterate).  helm_server_step advances every running column by
- * one outer FGMRES iteration, all columns of a group in the same kernel
- * launches, all groups enqueued before any is waited for (so groups overlap
- * on the device), and admits queued requests into free slots at that step
- * boundary, creating groups while their workspace fits the HBM budget and
- * releasing idle groups when space is needed.  A column's arithmetic does
- * not depend on which other columns share its launches, so a request's
- * result is the same alone and in the mix.
+ * column slots and one stream (another group of the same parameters is
+ * created when one is full); every column owns a slot (its own Krylov
+ * basis and iterate).  All columns of a group advance by one outer FGMRES
+ * iteration in the same kernel launches, and every group runs on its own
+ * stream at its own pace: helm_server_step polls the groups' in-flight
+ * iterations and, for each group whose iteration has finished on the
+ * device, completes it on the host, copies out its finished requests,
+ * admits queued requests into its free slots and enqueues its next
+ * iteration at once, while the other groups keep running; it returns once
+ * at least one group has advanced (or no group has work).  Groups are
+ * created while their workspace fits the HBM budget (computed from the
+ * sizes before anything is built) and idle groups are released when space
+ * is needed.  A column's arithmetic does not depend on which other columns
+ * share its launches, so a request's result is the same alone and in the
+ * mix.
  * The server allocates its workspaces itself (hipMalloc) and owns its
  * streams.  Not thread-safe.
  */
@@ -430,8 +436,9 @@ int helm_server_create(const helm_server_opts* opts, helm_server_t** out);
 int helm_server_submit(helm_server_t* s, int dim, int n, int levels, double k, double delta_hat,
                        const void* rhs, void* x, int nrhs, double tol, long long* id);
 
-/* One step of every running group plus admission; *n_done (nullable)
- * receives the number of requests completed by this step. */
+/* Advance the groups whose iterations have finished (see above) plus
+ * admission; *n_done (nullable) receives the number of requests completed
+ * by this call. */
 int helm_server_step(helm_server_t* s, int* n_done);
 
 int helm_server_query(const helm_server_t* s, long long id, helm_request_info* info);

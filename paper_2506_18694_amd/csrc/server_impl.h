@@ -2,6 +2,8 @@
 // batching of independent solves over per-group column engines.
 #pragma once
 
+#include <thread>
+
 namespace {
 
 struct Request {
@@ -46,6 +48,9 @@ struct Group {
         if (e64) e64->complete();
         else e32->complete();
     }
+    // an iteration is in flight on the device
+    bool pending() const { return e64 ? e64->pending : e32->pending; }
+    hipEvent_t event() const { return e64 ? e64->ev : e32->ev; }
 };
 
 }  // namespace
@@ -71,11 +76,42 @@ struct helm_server_s {
         g = Group{};
     }
 
-    // A group for request r: an existing one, or a new one if its workspace
-    // fits the budget (idle groups are released to make room).  -1 if none.
+    // Workspace bytes of a group for request r, from the sizes alone (the
+    // level table and the restart length helm_create would choose; nothing
+    // is allocated).
+    size_t plan_bytes(const Request& r) const {
+        helm_s t;
+        helm_opts_default(&t.opts);
+        t.dim = r.dim;
+        t.n = r.n;
+        t.levels = r.levels;
+        t.prec = opts.precision;
+        t.restart = opts.restart > 0 ? opts.restart : std::min(2000, 3 * (int)std::ceil(r.k) + 30);
+        for (int l = 0; l < r.levels; ++l) {
+            const int nl = r.n >> l;
+            long long Nl = 1;
+            for (int d = 0; d < r.dim; ++d) Nl *= (nl + 1);
+            t.nl.push_back(nl);
+            t.Nl.push_back(Nl);
+        }
+        t.nv = t.Nl[0];
+        return layout(&t, opts.max_cols).total;
+    }
+
+    // A group for request r: an existing one with room for its columns, or
+    // a new one (another of the same parameters when those are full) if its
+    // workspace fits the budget (idle groups are released to make room).
+    // -1 if none; a request that cannot fit builds nothing.
     int group_for(const Request& r) {
         for (int q = 0; q < (int)groups.size(); ++q)
-            if (groups[q].h && groups[q].matches(r)) return q;
+            if (groups[q].h && groups[q].matches(r) && groups[q].free_slots() >= r.nrhs) return q;
+        const size_t need = plan_bytes(r);
+        auto fits_need = [&]() { return in_use + (double)need <= opts.hbm_budget_bytes; };
+        if (!fits_need()) {
+            for (auto& other : groups)  // release idle groups if that makes room
+                if (!fits_need() && other.h && !other.busy() && !other.pending()) release(other);
+            if (!fits_need()) return -1;
+        }
         helm_mesh mesh{r.dim, r.dim == 2 ? HELM_P1_TRI_RIGHT : HELM_Q1_HEX, r.n, r.levels};
         helm_opts o;
         helm_opts_default(&o);
@@ -95,8 +131,6 @@ struct helm_server_s {
         }
         g.bytes = layout(g.h, opts.max_cols).total;
         auto fits = [&]() { return in_use + (double)g.bytes <= opts.hbm_budget_bytes; };
-        for (auto& other : groups)  // release idle groups if needed
-            if (!fits() && other.h && !other.busy()) release(other);
         if (!fits() || hipMalloc(&g.ws, g.bytes) != hipSuccess) {
             (void)helm_destroy(g.h);
             (void)hipStreamDestroy(g.stream);
@@ -137,17 +171,15 @@ struct helm_server_s {
         }
     }
 
-    int step() {
-        admit_queued();
-        for (auto& g : groups) g.enqueued = g.h && g.enqueue();
-        for (auto& g : groups)
-            if (g.enqueued) g.complete();
-        // completed requests: every column done
+    // Requests of group gi whose columns are all done: their solutions are
+    // copied out (stream-ordered after the group's last updates) and their
+    // slots freed.  Returns the number finished.
+    int collect(int gi) {
+        Group& g = groups[gi];
+        std::vector<Column>& cs = g.cols();
         int done = 0;
         for (auto& r : reqs) {
-            if (r.status != 1) continue;
-            Group& g = groups[r.group];
-            std::vector<Column>& cs = g.cols();
+            if (r.status != 1 || r.group != gi) continue;
             bool all = true;
             for (int c : r.cols) all = all && cs[c].phase == COL_DONE;
             if (!all) continue;
@@ -163,11 +195,49 @@ struct helm_server_s {
                 r.converged = r.converged && cs[c].converged;
                 r.true_rel = std::max(r.true_rel, cs[c].true_rel);
             }
-            HIPCHK(hipStreamSynchronize(g.stream));
             for (int c : r.cols) cs[c].phase = COL_FREE;
             r.status = 2;
-            r.t_done = now();
             ++done;
+        }
+        if (done) {
+            // the copies precede the group's next iteration on its stream
+            HIPCHK(hipStreamSynchronize(g.stream));
+            const double t = now();
+            for (auto& r : reqs)
+                if (r.status == 2 && r.group == gi && r.t_done == 0.0) r.t_done = t;
+        }
+        return done;
+    }
+
+    // Every group runs on its own stream at its own pace: a group whose
+    // iteration has finished on the device is completed at once (Givens
+    // rotations, finished requests copied out, queued requests admitted into
+    // its free slots) and its next iteration enqueued, while the others keep
+    // running.  Returns after at least one group has advanced, or when no
+    // group has work.
+    int step() {
+        int done = 0;
+        for (;;) {
+            admit_queued();
+            bool advanced = false, inflight = false;
+            for (int gi = 0; gi < (int)groups.size(); ++gi) {
+                if (!groups[gi].h) continue;
+                if (groups[gi].pending()) {
+                    const hipError_t e = hipEventQuery(groups[gi].event());
+                    if (e == hipErrorNotReady) {
+                        inflight = true;
+                        continue;
+                    }
+                    HIPCHK(e);
+                    groups[gi].complete();
+                    done += collect(gi);
+                    admit_queued();  // may add groups: index, do not hold references
+                    advanced = true;
+                }
+                if (groups[gi].h && groups[gi].enqueue()) inflight = true;
+            }
+            if (advanced || !inflight) break;
+            std::this_thread::yield();
         }
         return done;
     }

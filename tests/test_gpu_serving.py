@@ -1,6 +1,7 @@
 """Serving (continuous batching): requests arriving while others are on the
-GPU are admitted into free column slots at step boundaries, groups of
-different mesh sizes run concurrently, and every result equals the same
+GPU are admitted into free column slots at their group's iteration
+boundaries, groups of different mesh sizes run concurrently at their own
+pace, and every result equals the same
 request solved alone (bit for bit up to 1e-12 relative: a column's
 arithmetic does not depend on its neighbours) and the oracle's direct
 solve (1e-5 for the FP32-multigrid path, 1e-6 for FP64)."""
@@ -21,13 +22,17 @@ def _rhs(req, M):
     return np.stack([M @ fi for fi in f]).astype(np.complex128)
 
 
-@pytest.mark.parametrize("precision,tol_err", [("fp32", 1e-5), ("fp64", 1e-6)])
-def test_serving_mix_matches_alone_and_oracle(precision, tol_err):
+@pytest.mark.parametrize("precision,tol_err,sizes,count,max_cols", [
+    ("fp32", 1e-5, (32, 64), 10, 4), ("fp64", 1e-6, (32, 64), 10, 4),
+    # the register-streaming kernels on the finest levels; max_cols 3 makes
+    # the server open a second group of a size when the first is full
+    ("fp32", 1e-5, (128, 256), 8, 3)])
+def test_serving_mix_matches_alone_and_oracle(precision, tol_err, sizes, count, max_cols):
     from paper_2506_18694_amd import Server, Solver
-    reqs = W.serving_stream(10, sizes=(32, 64), max_rhs=3, seed=4)
+    reqs = W.serving_stream(count, sizes=sizes, max_rhs=3, seed=4)
     probs = {n: osolver.Problem(2, n, n / 10.0, n / 10.0, levels=int(np.log2(n / 8)) + 1)
-             for n in (32, 64)}
-    srv = Server(hbm_budget_bytes=8e9, max_cols=4, precision=precision)
+             for n in sizes}
+    srv = Server(hbm_budget_bytes=16e9, max_cols=max_cols, precision=precision)
     ids, xs, bs = {}, {}, {}
     pending = list(reqs)
     steps = 0
