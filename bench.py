@@ -207,12 +207,15 @@ def _oracle_direct_worker(name, out_path):
     import numpy as np
     from oracle import solver as osolver
     import workloads as W
+    log("[oracle worker %s] started" % name)
     w = W.WORKLOADS[name]
     pr = osolver.Problem(w["dim"], w["n"], w["k"], w["delta_hat"], levels=1)
+    log("[oracle worker %s] assembled" % name)
     f = W.workload_sources(name)
     U = np.stack([pr.solve_direct((pr.M @ fi).astype(np.complex128)) for fi in f])
     np.save(out_path + ".tmp.npy", U)
     os.replace(out_path + ".tmp.npy", out_path)
+    log("[oracle worker %s] direct solves done" % name)
 
 
 def start_oracle_worker(name, tmpdir):
@@ -288,14 +291,19 @@ def cpu_baseline(W, name, outer_its, cycles, sample_steps, info):
 
 
 def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1, restart=0,
-                time_cap=None):
+                time_cap=None, arrival_cap=None):
     """Continuous-batching run: requests arrive by a seeded Poisson process
     and are submitted when their arrival time passes; the server steps
-    continuously.  Latency = completion - arrival (wall clock)."""
+    continuously.  Latency = completion - arrival (wall clock).  With
+    arrival_cap, the stream is cut after the arrivals up to that time and
+    every request that arrived runs to completion (exact latencies of that
+    prefix of the stream)."""
     import numpy as np
     import torch
     from paper_2506_18694_amd import Server, Solver
     reqs = W.serving_stream(count, sizes=sizes, max_rhs=8, rate=rate, seed=seed)
+    if arrival_cap is not None:
+        reqs = [r for r in reqs if r["arrival"] <= arrival_cap]
     # load vectors b = M f on the device (set-up, untimed)
     loaders = {}
     rhs = []
@@ -353,7 +361,8 @@ def run_serving(W, count, sizes, rate, max_cols, budget_gb, precision, seed=1, r
     by_size = {}
     for i in finished:
         by_size.setdefault(reqs[i]["n"], []).append(lat[i])
-    return {"requests": len(reqs), "completed": len(finished), "sizes": list(sizes),
+    return {"requests": len(reqs), "stream_requests": count, "arrival_cap_s": arrival_cap,
+            "completed": len(finished), "sizes": list(sizes),
             "rate_per_s": rate, "max_cols": max_cols, "restart": restart,
             "precision": precision, "p50_latency_s": float(np.percentile(L, 50)),
             "p99_latency_s": float(np.percentile(L, 99)), "mean_latency_s": float(L.mean()),
@@ -547,13 +556,17 @@ def main():
                          "measured by a saturating batch of requests first")
     ap.add_argument("--max-cols", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=200.0)
-    ap.add_argument("--serving-restart", type=int, default=100,
-                    help="FGMRES basis per column in the serving groups")
+    ap.add_argument("--serving-restart", type=int, default=0,
+                    help="FGMRES basis per column in the serving groups (0: the library's "
+                         "3 ceil(k) + 30 for each group's k)")
     ap.add_argument("--probe-requests", type=int, default=32,
                     help="size of the saturating batch that measures capacity (rate auto)")
     ap.add_argument("--time-cap", type=float, default=None,
                     help="stop the serving run after this many seconds (latencies of the "
                          "completed requests are reported with the completed count)")
+    ap.add_argument("--arrival-cap", type=float, default=None,
+                    help="serve only the requests of the stream that arrive within this many "
+                         "seconds, each to completion")
     ap.add_argument("--paper", action="store_true",
                     help="run the paper's own settings (delta_hat = 2, uniform and box sources, "
                          "theta sweep, FGMRES and Richardson) and print their counts and rates")
@@ -621,7 +634,8 @@ def main():
         else:
             rate = float(args.rate)
         res = run_serving(W, args.requests, sizes, rate, args.max_cols, args.budget_gb, "fp32",
-                          restart=args.serving_restart, time_cap=args.time_cap)
+                          restart=args.serving_restart, time_cap=args.time_cap,
+                          arrival_cap=args.arrival_cap)
         res["capacity_req_per_s"] = capacity
         res["offered_load"] = rate / capacity if capacity else None
         out = {"metric": "serving p50/p99 latency (continuous batching, FP32-MG/FP64-outer)",
@@ -629,7 +643,8 @@ def main():
                "warmup": 0, "ms_per_step": res["makespan_s"] * 1e3, "higher_is_better": False,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
                "config": {"workload": "serving-2d-p1", **{k: v for k, v in res.items()
-                                                          if k in ("requests", "completed", "sizes",
+                                                          if k in ("requests", "stream_requests",
+                                                                   "arrival_cap_s", "completed", "sizes",
                                                                    "rate_per_s", "max_cols",
                                                                    "restart", "precision",
                                                                    "offered_load")}},
@@ -741,9 +756,14 @@ def main():
                               for fi in W.workload_sources(name)])
             elif name in workers:
                 p, path = workers[name]
-                p.join(timeout=max(1.0, budget - elapsed() - fixed_rest))
+                # the remaining configurations take a few seconds; keep the
+                # CPU baseline's share and a margin of the budget
+                p.join(timeout=max(1.0, budget - elapsed() - 60.0))
                 if os.path.exists(path):
                     U = np.load(path)
+                else:
+                    log("[bench] oracle direct solve of %s not finished (worker %s)"
+                        % (name, "running" if p.is_alive() else "exited %s" % p.exitcode))
             if U is not None:
                 ent["rel_l2_error_vs_oracle_direct"] = {"fp64": oracle_error(xs["fp64"], U),
                                                         "fp32_mg": oracle_error(xs["fp32"], U)}
