@@ -698,20 +698,23 @@ void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
 // or the first one-stage pass) and count its algorithmic bytes per column,
 // `bytes` vectors of the level.
 // The fused 3D sweeps in pairs (two stages per pass) in FP32, one per pass
-// in FP64 (whose two-stage kernels exceed the register budget).
+// in FP64 (whose two-stage kernels exceed the register budget; also on the
+// coarser levels, where halving the launches is worth less than the spills).
 #ifndef HELM_K3_TWO_STAGE_FP32
 #define HELM_K3_TWO_STAGE_FP32 1
 #endif
+#ifndef HELM_K3_TWO_STAGE_COARSE_FP64
+#define HELM_K3_TWO_STAGE_COARSE_FP64 0
+#endif
 template <typename T>
-constexpr bool two_stage3d() {
-    return sizeof(T) == 4 && HELM_K3_TWO_STAGE_FP32;
+constexpr bool two_stage3d(bool coarse) {
+    return sizeof(T) == 4 ? HELM_K3_TWO_STAGE_FP32 != 0 : (coarse && HELM_K3_TWO_STAGE_COARSE_FP64 != 0);
 }
 
 template <typename T>
 void sweeps3d(helm_t* h, const Op3F<T>& L, const Op3F<T>& B, int first, bool pro, int upd, T s,
               Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho,
-              Vec<cx<T>> Tmp, Vec<cx<T>> Y, int ns, bool prof = false, double bytes = 0.0) {
-    const bool two = two_stage3d<T>();
+              Vec<cx<T>> Tmp, Vec<cx<T>> Y, int ns, bool two, bool prof = false, double bytes = 0.0) {
     if (prof) h->prof_mark();
     if (two) {
         STREAMCHK((pass3d<T, T>(h->stream, L, B, first, 2, pro, upd, s, X, Bv, Ec, Rho, Y, ns)));
@@ -746,12 +749,13 @@ Vec<cx<T>> vcycle3d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const
     Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
     Vec<cx<T>> tc = at_ws<cx<T>>(ws, Lw.mg_t[l + 1], Nc);
     const Vec<const cx<T>> none{};
-    sweeps3d<T>(h, L, L, F_PRE0, false, 0, (T)1, none, b, none, Vec<cx<T>>{}, t, x, ns);
+    const bool two = two_stage3d<T>(true);
+    sweeps3d<T>(h, L, L, F_PRE0, false, 0, (T)1, none, b, none, Vec<cx<T>>{}, t, x, ns, two);
     rr3d<T>(h->stream, L, cst(x), b, bc, ns);
     Vec<cx<T>> ec = vcycle3d_zero<T>(h, Lw, ws, l + 1, cst(bc), xc, tc, ns);
     // the one-stage path ends in x (through t), the two-stage one in t
-    Vec<cx<T>> out = two_stage3d<T>() ? t : x;
-    sweeps3d<T>(h, L, L, F_JAC, true, 0, (T)1, cst(x), b, cst(ec), Vec<cx<T>>{}, t, out, ns);
+    Vec<cx<T>> out = two ? t : x;
+    sweeps3d<T>(h, L, L, F_JAC, true, 0, (T)1, cst(x), b, cst(ec), Vec<cx<T>>{}, t, out, ns, two);
     return out;
 }
 
@@ -779,13 +783,13 @@ void hss_step3d_fused(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const Vec<const cx<T>> none{};
     // the one-stage (FP64) sequence keeps the cycle's iterate in x, with t
     // between its two sweeps; the two-stage (FP32) one alternates x and t
-    const bool one = !two_stage3d<T>();
-    if (s == 0) sweeps3d<T>(h, L, Bs, F_HSS0, false, 0, c, none, cst(R), none, rho, t, x, ns);
-    else sweeps3d<T>(h, L, Bs, F_HSS, false, 0, c, cst(u), cst(R), none, rho, t, x, ns);
+    const bool two = two_stage3d<T>(false), one = !two;
+    if (s == 0) sweeps3d<T>(h, L, Bs, F_HSS0, false, 0, c, none, cst(R), none, rho, t, x, ns, two);
+    else sweeps3d<T>(h, L, Bs, F_HSS, false, 0, c, cst(u), cst(R), none, rho, t, x, ns, two);
     for (int q = 0; q < h->cycles; ++q) {
         if (q > 0) {
             sweeps3d<T>(h, L, L, F_JAC, false, 0, (T)1, cst(x), cst(rho), none, Vec<cx<T>>{}, t,
-                        one ? x : t, ns);
+                        one ? x : t, ns, two);
             if (!one) std::swap(x, t);
         }
         rr3d<T>(h->stream, L, cst(x), cst(rho), b1, ns);
@@ -797,10 +801,10 @@ void hss_step3d_fused(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
         const bool prof = h->prof_on && !last && s % helm_s::PROF_EVERY == 0;
         if (last) {
             sweeps3d<T>(h, L, L, F_JAC, true, s > 0 ? 1 : 0, (T)1, cst(x), cst(rho), ec, Vec<cx<T>>{},
-                        t, u, ns);
+                        t, u, ns, two);
         } else {
             sweeps3d<T>(h, L, L, F_JAC, true, 0, (T)1, cst(x), cst(rho), ec, Vec<cx<T>>{}, t,
-                        one ? x : t, ns, prof, 3.125 * (double)N);
+                        one ? x : t, ns, two, prof, 3.125 * (double)N);
             if (!one) std::swap(x, t);
         }
     }

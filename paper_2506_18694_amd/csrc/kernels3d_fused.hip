@@ -435,7 +435,9 @@ template <typename T>
 __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<const cx<T>> Bv,
                                             Vec<cx<T>> Bc, Grid3F g) {
     __shared__ cx<T> pin[2][LW][LW];
-    __shared__ cx<T> pres[LW][LW];
+    // residual plane with the even and odd columns of a row stored apart, so
+    // that the coarse columns of the second stage read consecutive words
+    __shared__ cx<T> pres[LW][2][LW / 2];
     int slot, tx, ty, seg;
     unit_of(g, slot, tx, ty, seg);
     const int n = L.n, nc = n / 2;
@@ -505,11 +507,17 @@ __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<c
         if (st1 && inmesh && q >= 0 && q <= n) r = bcur - (acc + t1);
         acc = T1p + t0;
         T1p = t1;
-        pres[ly][lx] = r;
+        pres[ly][lx & 1][lx >> 1] = r;
         __syncthreads();
         if (cst) {
             cx<T> c0, cH, cV, c2;
-            plane_sums<T>(pres, 2 * cj + 2, 2 * ci + 2, c0, cH, cV, c2);
+            // fine centre (2 cj + 2, 2 ci + 2): even column ci + 1, its
+            // neighbours the odd columns ci and ci + 1 of the same rows
+            const int r0 = 2 * cj + 2;
+            c0 = pres[r0][0][ci + 1];
+            cH = pres[r0][1][ci] + pres[r0][1][ci + 1];
+            cV = pres[r0 - 1][0][ci + 1] + pres[r0 + 1][0][ci + 1];
+            c2 = (pres[r0 - 1][1][ci] + pres[r0 - 1][1][ci + 1]) + (pres[r0 + 1][1][ci] + pres[r0 + 1][1][ci + 1]);
             const cx<T> r2 = c0 + (T)0.5 * (cH + cV) + (T)0.25 * c2;
             if (kb == 0) {  // q odd
                 const int Lc = (q - 1) >> 1;  // coarse plane completed by this odd plane
@@ -553,9 +561,15 @@ int resident_units() {
 
 // Segment height: output planes per workgroup.  A launch takes
 // ceil(units / resident) rounds, each as long as one segment's march (its
-// planes plus a pipeline head of about four); the height minimises
-// rounds x (planes + 4), at least 8 planes unless one segment covers the
-// level.
+// planes plus a pipeline head of about HEAD planes); the height minimises
+// rounds x (planes + HEAD), at least MINTZ planes unless one segment
+// covers the level.
+#ifndef HELM_K3_MINTZ
+#define HELM_K3_MINTZ 2
+#endif
+#ifndef HELM_K3_HEAD
+#define HELM_K3_HEAD 4
+#endif
 int seg_planes(int planes, int tiles, int nslots, int resident) {
 #ifdef HELM_K3_SEGS
     return (planes + HELM_K3_SEGS - 1) / HELM_K3_SEGS;
@@ -565,10 +579,10 @@ int seg_planes(int planes, int tiles, int nslots, int resident) {
     long long best_cost = -1;
     for (int segs = 1; segs <= planes; ++segs) {
         const int tz = (planes + segs - 1) / segs;
-        if (tz < 8 && segs > 1) break;
+        if (tz < HELM_K3_MINTZ && segs > 1) break;
         const long long units = (long long)tiles * segs * nslots;
         const long long rounds = (units + cus - 1) / cus;
-        const long long cost = rounds * (tz + 4);
+        const long long cost = rounds * (tz + HELM_K3_HEAD);
         if (best_cost < 0 || cost < best_cost) {
             best_cost = cost;
             best = tz;
