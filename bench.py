@@ -201,9 +201,14 @@ def roofline(dim, name, precision, stats):
 
 
 # ---------------------------------------------------------------- oracle side --
-def _oracle_direct_worker(name, out_path):
+def _oracle_direct_worker(name, out_path, threads):
     """CPU worker: the oracle's direct solves B_0 u = b of a workload's
-    right-hand sides (sparse LU), saved for the error of the GPU solves."""
+    right-hand sides (sparse LU), saved for the error of the GPU solves.
+    Its BLAS threads are capped (set before numpy loads): with every
+    worker's threads plus the GPU process's on the same cores, spinning BLAS
+    threads slowed the factorisation by more than ten times."""
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = str(threads)
     import numpy as np
     from oracle import solver as osolver
     import workloads as W
@@ -218,12 +223,13 @@ def _oracle_direct_worker(name, out_path):
     log("[oracle worker %s] direct solves done" % name)
 
 
-def start_oracle_worker(name, tmpdir):
+def start_oracle_worker(name, tmpdir, threads=4):
     import multiprocessing as mp
     out = os.path.join(tmpdir, "oracle_%s.npy" % name)
     if os.path.exists(out):
         os.remove(out)
-    p = mp.get_context("spawn").Process(target=_oracle_direct_worker, args=(name, out), daemon=True)
+    p = mp.get_context("spawn").Process(target=_oracle_direct_worker, args=(name, out, threads),
+                                        daemon=True)
     p.start()
     return p, out
 

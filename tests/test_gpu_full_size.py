@@ -116,9 +116,13 @@ def test_headline_solve_true_residual(head, head_direct, prec, err_tol):
     x, st = s.solve(b, tol=1e-8)
     assert st["converged"]
     bh, xh = to_host(b), to_host(x)
+    errs = []
     for bi, xi, ui in zip(bh, xh, head_direct):
         assert np.linalg.norm(bi - pr.B0 @ xi) / np.linalg.norm(bi) <= 1.01e-8
-        assert rel_l2(xi, ui) <= err_tol
+        errs.append(rel_l2(xi, ui))
+    print("%s %s rel l2 error vs oracle direct per column: %s"
+          % (HEAD, prec, " ".join("%.3e" % e for e in errs)))
+    assert max(errs) <= err_tol
     # the load vector itself against the oracle's mass matrix
     fh = W.workload_sources(HEAD)
     assert rel_err(bh, np.stack([pr.M @ fi for fi in fh])) < 1e-12
