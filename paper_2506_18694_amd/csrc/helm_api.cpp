@@ -706,9 +706,13 @@ void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
 #ifndef HELM_K3_TWO_STAGE_COARSE_FP64
 #define HELM_K3_TWO_STAGE_COARSE_FP64 0
 #endif
+#ifndef HELM_K3_TWO_STAGE_FP64
+#define HELM_K3_TWO_STAGE_FP64 0
+#endif
 template <typename T>
 constexpr bool two_stage3d(bool coarse) {
-    return sizeof(T) == 4 ? HELM_K3_TWO_STAGE_FP32 != 0 : (coarse && HELM_K3_TWO_STAGE_COARSE_FP64 != 0);
+    return sizeof(T) == 4 ? HELM_K3_TWO_STAGE_FP32 != 0
+                          : (HELM_K3_TWO_STAGE_FP64 != 0 || (coarse && HELM_K3_TWO_STAGE_COARSE_FP64 != 0));
 }
 
 template <typename T>

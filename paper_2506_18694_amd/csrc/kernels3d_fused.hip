@@ -52,7 +52,7 @@ constexpr int LW = 32;
 constexpr int FT = LW * LW;  // threads per workgroup
 constexpr int RC = 14;       // coarse columns per tile side in the restriction
 #ifndef HELM_K3_PF
-#define HELM_K3_PF 3
+#define HELM_K3_PF 2
 #endif
 constexpr int PF = HELM_K3_PF;  // input planes requested ahead of the one in LDS (>= 1)
 
@@ -591,6 +591,25 @@ int seg_planes(int planes, int tiles, int nslots, int resident) {
     return best;
 }
 
+// The same for the restriction, whose segments own coarse planes and march
+// two fine planes per coarse one (plus a head of about HEAD + 2).
+int seg_planes_rr(int cplanes, int tiles, int nslots, int resident) {
+    int best = cplanes;
+    long long best_cost = -1;
+    for (int tz = cplanes; tz >= 1; --tz) {
+        const int segs = (cplanes + tz - 1) / tz;
+        if (tz < HELM_K3_MINTZ && segs > 1) break;
+        const long long units = (long long)tiles * segs * nslots;
+        const long long rounds = (units + resident - 1) / resident;
+        const long long cost = rounds * (2LL * tz + HELM_K3_HEAD + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = tz;
+        }
+    }
+    return best;
+}
+
 template <typename T, typename TI, int F, int NS, bool PRO, int UPD>
 void launch_pass(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
                  Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
@@ -651,9 +670,7 @@ void rr3d(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>>
     Grid3F g;
     g.tiles_x = (nc + 1 + RC - 1) / RC;
     g.tiles_y = g.tiles_x;
-    g.tz = tz > 0 ? tz
-                  : std::max(4, seg_planes(2 * nc + 1, g.tiles_x * g.tiles_y, nslots,
-                                           resident_units<k3_rr<T>>()) / 2);
+    g.tz = tz > 0 ? tz : seg_planes_rr(nc + 1, g.tiles_x * g.tiles_y, nslots, resident_units<k3_rr<T>>());
     g.segs = (nc + 1 + g.tz - 1) / g.tz;
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
     k3_rr<T><<<grid, FT, 0, st>>>(L, X, Bv, Bc, g);
