@@ -45,12 +45,30 @@ namespace helm {
 
 namespace {
 
-// A workgroup of LW x LW threads stages one LW x LW region of an input plane
+// A workgroup of LW x H threads stages one LW x H region of an input plane
 // (one value per thread); the first stage runs on its interior
-// (LW - 2)^2 columns, the second stage on the (LW - 4)^2 inside that.
-constexpr int LW = 32;
-constexpr int FT = LW * LW;  // threads per workgroup
-constexpr int RC = 14;       // coarse columns per tile side in the restriction
+// (LW - 2) x (H - 2) columns, the second stage on the (LW - 4) x (H - 4)
+// inside that.
+// Tile rows by precision: FP64 tiles are 32 x 32 (1024 threads; its passes
+// are bound by HBM, so the smallest halo share wins), FP32 tiles 32 x 16
+// (512 threads: its passes are bound by issue and the two barriers per
+// plane, and two 512-thread workgroups per CU overlap each other's
+// barriers).
+#ifndef HELM_K3_LH_FP64
+#define HELM_K3_LH_FP64 32
+#endif
+#ifndef HELM_K3_LH_FP32
+#define HELM_K3_LH_FP32 16
+#endif
+constexpr int LW = 32;            // tile columns (x)
+constexpr int RC = (LW - 4) / 2;  // coarse columns per tile in the restriction
+template <typename T>
+struct Tile {
+    static constexpr int H = sizeof(T) == 4 ? HELM_K3_LH_FP32 : HELM_K3_LH_FP64;  // tile rows (y)
+    static constexpr int FT = LW * H;           // threads per workgroup
+    static constexpr int RCH = (H - 4) / 2;     // coarse rows per tile in the restriction
+    static constexpr int CWH = H / 2 + 1;       // coarse rows under a tile (prolongation)
+};
 #ifndef HELM_K3_PF
 #define HELM_K3_PF 2
 #endif
@@ -129,7 +147,7 @@ __device__ __forceinline__ void plane_terms(const Op3F<T>& op, bool edge_wave, c
     if (bz) T0 = cfma(nb * op.f0[0] + bxy * op.f0[2], a0, cfma(op.f0[1], w, T0));
 }
 
-// in-plane sums at (row r, column q) of an LW x LW LDS plane
+// in-plane sums at (row r, column q) of an LDS plane of LW columns
 template <typename T>
 __device__ __forceinline__ void plane_sums(const cx<T> (*pl)[LW], int r, int q, cx<T>& a0, cx<T>& H,
                                            cx<T>& V, cx<T>& a2) {
@@ -167,7 +185,7 @@ __device__ __forceinline__ void unit_of(const Grid3F& g, int& slot, int& tx, int
 // of the two LDS buffers; the last partial block runs guarded steps.
 constexpr int UNR = 6;
 static_assert(UNR % PF == 0 && UNR % 2 == 0, "unroll must cover the rings and the LDS buffers");
-constexpr int CW = LW / 2 + 1;  // coarse columns per side under a tile (prolongation)
+constexpr int CW = LW / 2 + 1;  // coarse columns under a tile (prolongation)
 
 template <int U>
 using IC = std::integral_constant<int, U>;
@@ -193,26 +211,27 @@ using IC = std::integral_constant<int, U>;
 // plane for fine step p is written to LDS one step ahead and requested two
 // steps ahead of that; the march then starts on an even plane.
 template <typename T, typename TI, int FIRST, int NS, bool PRO, int UPD>
-__global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<const cx<TI>> X,
+__global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<const cx<TI>> X,
                                               Vec<const cx<T>> Bv, Vec<const cx<T>> Ec,
                                               Vec<cx<T>> Rho, Vec<cx<T>> Y, Grid3F g) {
     constexpr bool PW = FIRST == F_HSS0 || FIRST == F_PRE0;
     constexpr bool HSS = FIRST == F_HSS || FIRST == F_HSS0;
-    constexpr int OWN = LW - 2 * NS;  // owned columns per tile side
+    constexpr int LH = Tile<T>::H, CWH = Tile<T>::CWH;
+    constexpr int OWN = LW - 2 * NS, OWNH = LH - 2 * NS;  // owned columns and rows of a tile
     static_assert(!(PRO && PW), "the prolongation feeds a stencil first stage");
-    __shared__ cx<T> pin[2][LW][LW];
-    __shared__ cx<T> pmid[LW][LW];
-    __shared__ cx<T> cpl[PRO ? 2 : 1][PRO ? CW : 1][PRO ? CW : 1];
+    __shared__ cx<T> pin[2][LH][LW];
+    __shared__ cx<T> pmid[LH][LW];
+    __shared__ cx<T> cpl[PRO ? 2 : 1][PRO ? CWH : 1][PRO ? CW : 1];
     int slot, tx, ty, seg;
     unit_of(g, slot, tx, ty, seg);
     const int n = L.n;
     const long long sy = n + 1, sz = sy * sy;
     const int lx = (int)threadIdx.x % LW, ly = (int)threadIdx.x / LW;
-    const int i0 = tx * OWN - NS, j0 = ty * OWN - NS;  // first column of the tile
+    const int i0 = tx * OWN - NS, j0 = ty * OWNH - NS;  // first column of the tile
     const int i = i0 + lx, j = j0 + ly;                 // this thread's column
     const bool inmesh = (i >= 0) & (i <= n) & (j >= 0) & (j <= n);
-    const bool st1 = (lx >= 1) & (lx < LW - 1) & (ly >= 1) & (ly < LW - 1);
-    const bool st2 = (lx >= 2) & (lx < LW - 2) & (ly >= 2) & (ly < LW - 2);
+    const bool st1 = (lx >= 1) & (lx < LW - 1) & (ly >= 1) & (ly < LH - 1);
+    const bool st2 = (lx >= 2) & (lx < LW - 2) & (ly >= 2) & (ly < LH - 2);
     const bool owned = inmesh & (NS == 2 ? st2 : st1);
     const bool bx = (i == 0) | (i == n), by = (j == 0) | (j == n);
     const bool edge_wave = __any((int)(inmesh & (bx | by)));
@@ -242,13 +261,13 @@ __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<con
     auto ldcol = [&](const cx<T>* p, int l, int hi) { return ldo(p + pl(l, hi), ob); };
     auto lok = [&](int l) { return inmesh && l >= 0 && l <= n; };
     // prolongation: this thread's coarse corner in the tile's LDS coarse
-    // plane, and the coarse value it stages (threads 0 .. CW^2 - 1)
+    // plane, and the coarse value it stages (threads 0 .. CW CWH - 1)
     const int nc = n / 2;
     const long long syc = nc + 1, szc = syc * syc;
     const int cI0 = i0 >> 1, cJ0 = j0 >> 1;  // floor: i0 may be negative
     const int ci = (i >> 1) - cI0, cj = (j >> 1) - cJ0, cdx = i & 1, cdy = j & 1;
     const int ca = (int)threadIdx.x % CW, cb = (int)threadIdx.x / CW;
-    const bool cld = PRO && (int)threadIdx.x < CW * CW;
+    const bool cld = PRO && (int)threadIdx.x < CW * CWH;
     const bool cin = cld && cI0 + ca >= 0 && cI0 + ca <= nc && cJ0 + cb >= 0 && cJ0 + cb <= nc;
     const cx<T>* ecs = PRO ? Ec.at(slot) : nullptr;
     const unsigned oc = cin ? (unsigned)((cJ0 + cb) * syc + (cI0 + ca)) * (unsigned)sizeof(cx<T>) : 0u;
@@ -432,12 +451,13 @@ __global__ __launch_bounds__(FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<con
 // planes [Z0, Z0 + tz).  The march starts on an even plane and is unrolled
 // as in k3_pass.
 template <typename T>
-__global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<const cx<T>> Bv,
-                                            Vec<cx<T>> Bc, Grid3F g) {
-    __shared__ cx<T> pin[2][LW][LW];
+__global__ __launch_bounds__(Tile<T>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<const cx<T>> Bv,
+                                                     Vec<cx<T>> Bc, Grid3F g) {
+    constexpr int LH = Tile<T>::H, RCH = Tile<T>::RCH;
+    __shared__ cx<T> pin[2][LH][LW];
     // residual plane with the even and odd columns of a row stored apart, so
     // that the coarse columns of the second stage read consecutive words
-    __shared__ cx<T> pres[LW][2][LW / 2];
+    __shared__ cx<T> pres[LH][2][LW / 2];
     int slot, tx, ty, seg;
     unit_of(g, slot, tx, ty, seg);
     const int n = L.n, nc = n / 2;
@@ -445,9 +465,9 @@ __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<c
     const int lx = (int)threadIdx.x % LW, ly = (int)threadIdx.x / LW;
     // staged column; the residual is formed on the region's interior, whose
     // first column 2 RC tx - 1 is the fine neighbour left of coarse column RC tx
-    const int i = 2 * RC * tx - 2 + lx, j = 2 * RC * ty - 2 + ly;
+    const int i = 2 * RC * tx - 2 + lx, j = 2 * RCH * ty - 2 + ly;
     const bool inmesh = (i >= 0) & (i <= n) & (j >= 0) & (j <= n);
-    const bool st1 = (lx >= 1) & (lx < LW - 1) & (ly >= 1) & (ly < LW - 1);
+    const bool st1 = (lx >= 1) & (lx < LW - 1) & (ly >= 1) & (ly < LH - 1);
     const bool bx = (i == 0) | (i == n), by = (j == 0) | (j == n);
     const bool edge_wave = __any((int)(inmesh & (bx | by)));
     const long long col = inmesh ? (long long)j * sy + i : 0;
@@ -459,9 +479,9 @@ __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<c
     const cx<T> z = mk((T)0, (T)0);
     // coarse column of the second stage (threads 0 .. RC^2 - 1); its fine
     // centre (2 I, 2 J) is staged at (2 ci + 2, 2 cj + 2)
-    const bool cst = (int)threadIdx.x < RC * RC;
+    const bool cst = (int)threadIdx.x < RC * RCH;
     const int ci = (int)threadIdx.x % RC, cj = (int)threadIdx.x / RC;
-    const int I = RC * tx + ci, J = RC * ty + cj;
+    const int I = RC * tx + ci, J = RCH * ty + cj;
     const bool cown = cst & (I <= nc) & (J <= nc);
     const unsigned occ = cown ? (unsigned)(J * syc + I) * (unsigned)sizeof(cx<T>) : 0u;
 
@@ -546,7 +566,7 @@ __global__ __launch_bounds__(FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<c
 
 // Workgroups of a kernel that the device holds at once (its occupancy per
 // CU, from its register and LDS use, times the CUs), asked once per kernel.
-template <auto K>
+template <auto K, int FT>
 int resident_units() {
     static const int units = [] {
         int nb = 0, dev = 0, cus = 0;
@@ -614,16 +634,16 @@ template <typename T, typename TI, int F, int NS, bool PRO, int UPD>
 void launch_pass(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
                  Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
                  int tz) {
-    const int n = L.n, own = LW - 2 * NS;
+    const int n = L.n, own = LW - 2 * NS, ownh = Tile<T>::H - 2 * NS;
     Grid3F g;
     g.tiles_x = (n + 1 + own - 1) / own;
-    g.tiles_y = g.tiles_x;
+    g.tiles_y = (n + 1 + ownh - 1) / ownh;
     g.tz = tz > 0 ? tz
                   : seg_planes(n + 1, g.tiles_x * g.tiles_y, nslots,
-                               resident_units<k3_pass<T, TI, F, NS, PRO, UPD>>());
+                               resident_units<k3_pass<T, TI, F, NS, PRO, UPD>, Tile<T>::FT>());
     g.segs = (n + 1 + g.tz - 1) / g.tz;
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
-    k3_pass<T, TI, F, NS, PRO, UPD><<<grid, FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g);
+    k3_pass<T, TI, F, NS, PRO, UPD><<<grid, Tile<T>::FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g);
 }
 
 }  // namespace
@@ -669,11 +689,12 @@ void rr3d(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>>
     const int nc = L.n / 2;
     Grid3F g;
     g.tiles_x = (nc + 1 + RC - 1) / RC;
-    g.tiles_y = g.tiles_x;
-    g.tz = tz > 0 ? tz : seg_planes_rr(nc + 1, g.tiles_x * g.tiles_y, nslots, resident_units<k3_rr<T>>());
+    g.tiles_y = (nc + 1 + Tile<T>::RCH - 1) / Tile<T>::RCH;
+    g.tz = tz > 0 ? tz
+                  : seg_planes_rr(nc + 1, g.tiles_x * g.tiles_y, nslots, resident_units<k3_rr<T>, Tile<T>::FT>());
     g.segs = (nc + 1 + g.tz - 1) / g.tz;
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
-    k3_rr<T><<<grid, FT, 0, st>>>(L, X, Bv, Bc, g);
+    k3_rr<T><<<grid, Tile<T>::FT, 0, st>>>(L, X, Bv, Bc, g);
 }
 
 template bool pass3d<double, double>(hipStream_t, const Op3F<double>&, const Op3F<double>&, int, int,
