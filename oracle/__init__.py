@@ -12,7 +12,8 @@ library.
 
 Modules
 -------
-fem        meshes, element matrices, global assembly, interpolation (Sec. 2)
+fem        meshes, element matrices, global assembly, interpolation, and the
+           elimination of Dirichlet faces (Sec. 2)
 operators  B_delta, the H inner product, A_S, and the HSS operators L, N
            (Sec. 3.1 and the shifted-HSS definition of Sec. 4)
 hss        the gamma=k HSS iteration in its literal and correction forms, and

@@ -317,6 +317,46 @@ def nodes(dim, n):
     return nodes_2d(n) if dim == 2 else nodes_3d(n)
 
 
+def dirichlet_node_mask(dim, n, dirichlet):
+    """True at the nodes lying on any of the faces named in `dirichlet`
+    ("x0" is the face x = 0, "x1" the face x = 1, and so on)."""
+    names = FACES_2D if dim == 2 else FACES_3D
+    for f in dirichlet:
+        if f not in names:
+            raise ValueError("unknown face " + repr(f))
+    X = nodes(dim, n)
+    mask = np.zeros(X.shape[0], dtype=bool)
+    for f in dirichlet:
+        ax = "xyz".index(f[0])
+        mask |= np.isclose(X[:, ax], 0.0 if f[1] == "0" else 1.0)
+    return mask
+
+
+def impedance_faces(dim, dirichlet):
+    """The faces that keep the boundary (impedance) term when the faces in
+    `dirichlet` carry u = 0 instead: the rest of the boundary."""
+    names = FACES_2D if dim == 2 else FACES_3D
+    return tuple(f for f in names if f not in dirichlet)
+
+
+def eliminate(A, mask):
+    """Homogeneous Dirichlet conditions by elimination: the nodes in `mask`
+    leave the unknowns, so their rows and columns are removed from A and,
+    to keep one index per node, replaced by those of the identity.  The
+    system A' x = b with b = 0 on those nodes then has x = 0 there and the
+    reduced system on the other nodes."""
+    keep = sp.diags((~mask).astype(np.float64))
+    return (keep @ A @ keep + sp.diags(mask.astype(np.float64))).tocsr()
+
+
+def restrict_prolongation(P, fine_mask, coarse_mask):
+    """Interpolation between the spaces with the Dirichlet nodes removed:
+    P with the rows of fine Dirichlet nodes and the columns of coarse
+    Dirichlet nodes set to zero."""
+    return (sp.diags((~fine_mask).astype(np.float64)) @ P
+            @ sp.diags((~coarse_mask).astype(np.float64))).tocsr()
+
+
 # ----------------------------------------------- quadrature load vectors ---
 
 def _gauss01(q):

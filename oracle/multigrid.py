@@ -45,18 +45,30 @@ class Level:
 
 
 class Hierarchy:
-    """Levels 0 (finest, n cells per side) to levels-1 (n / 2^(levels-1))."""
+    """Levels 0 (finest, n cells per side) to levels-1 (n / 2^(levels-1)).
 
-    def __init__(self, dim, n, levels, abc, faces=None):
+    `dirichlet` names faces with u = 0 (e.g. ("x0", "x1")): on every level
+    their nodes are eliminated (`fem.eliminate`), the boundary term stays on
+    the other faces, and P interpolates between the reduced spaces
+    (`fem.restrict_prolongation`)."""
+
+    def __init__(self, dim, n, levels, abc, faces=None, dirichlet=()):
         if n % (2 ** (levels - 1)) != 0:
             raise ValueError("n must be divisible by 2^(levels-1)")
         self.dim = dim
         self.levels = []
+        if dirichlet and faces is None:
+            faces = fem.impedance_faces(dim, dirichlet)
         for l in range(levels):
             nl = n // (2 ** l)
             K, M, MG = fem.assemble(dim, nl, faces)
             A = combine(K, M, MG, abc)
             P = fem.prolongation(dim, nl) if l < levels - 1 else None
+            if dirichlet:
+                A = fem.eliminate(A, fem.dirichlet_node_mask(dim, nl, dirichlet))
+                if P is not None:
+                    P = fem.restrict_prolongation(P, fem.dirichlet_node_mask(dim, nl, dirichlet),
+                                                  fem.dirichlet_node_mask(dim, nl // 2, dirichlet))
             self.levels.append(Level(nl, A, P))
         self._coarse_lu = None
 

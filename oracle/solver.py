@@ -49,20 +49,28 @@ def nested_dissection_2d(n1, leaf=6):
 
 class Problem:
     def __init__(self, dim, n, k, delta_hat, delta=0.0, levels=1, faces=None,
-                 nu1=2, nu2=2, omega=2.0 / 3.0, m=1, cycles=2, cycle="v", smooth_its=5):
+                 nu1=2, nu2=2, omega=2.0 / 3.0, m=1, cycles=2, cycle="v", smooth_its=5,
+                 dirichlet=()):
         self.dim, self.n, self.k = dim, n, float(k)
         self.delta, self.delta_hat = float(delta), float(delta_hat)
         self.nu1, self.nu2, self.omega, self.m = nu1, nu2, omega, m
         self.cycles = cycles            # cycles per inner HSS solve
         self.cycle = cycle              # "v": V(nu1, nu2) Jacobi; "w": the
         self.smooth_its = smooth_its    # paper's W-cycle, GMRES_its smoothing
+        # faces with u = 0: their nodes are eliminated from every operator
+        # and the boundary term lives on the remaining faces
+        self.dirichlet = tuple(dirichlet)
+        if self.dirichlet and faces is None:
+            faces = fem.impedance_faces(dim, self.dirichlet)
+        self.fixed = fem.dirichlet_node_mask(dim, n, self.dirichlet)
         self.K, self.M, self.MG = fem.assemble(dim, n, faces)
         K, M, MG = self.K, self.M, self.MG
-        self.B0 = ops.b_delta(K, M, MG, k, delta).tocsr()
-        self.Bdh = ops.b_delta(K, M, MG, k, delta_hat).tocsr()
-        self.L = ops.hss_lhs(K, M, MG, k, delta_hat).tocsr()
-        self.N = ops.hss_rhs(K, M, MG, k, delta_hat).tocsr()
-        self.H = ops.h_gram(M, MG, k, delta_hat).tocsr()
+        elim = (lambda A: fem.eliminate(A, self.fixed)) if self.dirichlet else (lambda A: A)
+        self.B0 = elim(ops.b_delta(K, M, MG, k, delta).tocsr())
+        self.Bdh = elim(ops.b_delta(K, M, MG, k, delta_hat).tocsr())
+        self.L = elim(ops.hss_lhs(K, M, MG, k, delta_hat).tocsr())
+        self.N = elim(ops.hss_rhs(K, M, MG, k, delta_hat).tocsr())
+        self.H = elim(ops.h_gram(M, MG, k, delta_hat).tocsr())
         self.levels = levels
         self._lu_L = None
         self._lu_B0 = None
@@ -101,7 +109,8 @@ class Problem:
     def hierarchy(self):
         if self._hier is None:
             abc = ops.coefficients("L", self.k, self.delta_hat)
-            self._hier = multigrid.Hierarchy(self.dim, self.n, self.levels, abc, self.faces)
+            self._hier = multigrid.Hierarchy(self.dim, self.n, self.levels, abc, self.faces,
+                                             self.dirichlet)
         return self._hier
 
     def vcycle(self, b):
