@@ -119,9 +119,16 @@ typedef struct {
 
 typedef struct {
     /* Bit f set means face f carries u = 0 (Dirichlet) instead of the
-       Sommerfeld condition: x0=1, x1=2, y0=4, y1=8, z0=16, z1=32.
-       This build implements Sommerfeld on every face: any set bit gives
-       HELM_ENOTSUP. */
+       impedance (Sommerfeld) condition of Sec. 2: x0=1, x1=2, y0=4, y1=8,
+       z0=16, z1=32 (only the first four in 2D).  The nodes of those faces
+       are not unknowns: every operator keeps the rows and columns of the
+       other nodes (the impedance term lives on the remaining faces) and
+       acts as the identity on Dirichlet nodes, the prolongation P drops
+       them on both levels, and the coarsest-mesh matrix gets identity rows
+       and columns there.  Every vector a call writes is zero on Dirichlet
+       nodes; vectors passed to the per-step calls must be zero there too
+       (helm_solve and helm_precondition zero their inputs there
+       themselves).  Primal P1/Q1 element with V cycles only. */
     unsigned dirichlet_faces;
 } helm_bc;
 
@@ -255,8 +262,9 @@ const char* helm_last_error(void);
  * levels < 1, n not divisible by 2^(levels-1), k <= 0, delta < 0,
  * delta_hat <= delta, hss_m < 1, omega not in (0, 2), out == NULL, an
  * unknown outer or cycle, smooth_its outside 0..20, or (V cycles) a
- * coarsest mesh with more than 4096 nodes; HELM_ENOTSUP for Dirichlet
- * faces, (nu1, nu2) != (2, 2) with V cycles, or the W variant with
+ * coarsest mesh with more than 4096 nodes, or dirichlet_faces bits beyond
+ * the 2 dim faces; HELM_ENOTSUP for Dirichlet faces with the mixed element or the
+ * W variant, (nu1, nu2) != (2, 2) with V cycles, or the W variant with
  * HELM_FP32_MG or with the mixed element; HELM_ENOMEM; HELM_EDEVICE.
  * On error *out is set to NULL and nothing is leaked.
  */

@@ -140,6 +140,11 @@ struct Engine {
             HIPCHK(hipMemcpyAsync(Xb() + (long long)c * N, x0, sizeof(cxd) * N, hipMemcpyDeviceToDevice, s));
         else
             zero<double>(s, Xb() + (long long)c * N, N);
+        // Dirichlet nodes are not unknowns: the rhs and guess are zero there
+        if (h->dir && !h->mixed) {
+            dir_mask<double>(h, s, 0, Vec<cxd>{Bb() + (long long)c * N, N, 0, nullptr}, 1);
+            dir_mask<double>(h, s, 0, Vec<cxd>{Xb() + (long long)c * N, N, 0, nullptr}, 1);
+        }
         return c;
     }
 
@@ -153,6 +158,7 @@ struct Engine {
             stencil2d<double, double>(s, make_op2<double>(b0, h->n, h->omega), mode, 1.0, X, Bv, Y, ns);
         else
             op3d<double, double>(h, s, b0, 0, mode, 1.0, X, Bv, Y, ns);
+        dir_mask<double>(h, s, 0, Y, ns);
     }
     void apply_BZ(Vec<const cx<T>> Zv, Vec<cxd> Y, int ns) {
         if (h->mixed) {
@@ -165,6 +171,7 @@ struct Engine {
                                  Vec<const cxd>{}, Y, ns);
         else
             op3d<double, T>(h, s, b0, 0, MODE_APPLY, 1.0, Zv, Vec<const cxd>{}, Y, ns);
+        dir_mask<double>(h, s, 0, Y, ns);
     }
 
     // Enqueue one step's device work.  Returns false if nothing to do.

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/helm.h"
+#include "faces.h"
 #include "launch.h"
 #include "stencil_rows.h"
 
@@ -303,6 +304,15 @@ struct helm_s {
     bool mixed = false;
     long long nv = 0;  // unknowns per column: N, or N + 4 n^2 (mixed)
 
+    // Dirichlet faces (u = 0; bit f: x0 x1 y0 y1 z0 z1).  Their nodes are
+    // not unknowns: every vector the library produces is zero there, and
+    // the operators' rows on the other nodes are those of the Sommerfeld
+    // operator (whose couplings to the face nodes meet zeros).  Such handles
+    // run the one-pass-per-launch path with the faces cleared after every
+    // pass (the fused passes would carry nonzero face values between their
+    // internal sweeps).
+    unsigned dir = 0;
+
     Coef coef(int op) const {
         if (mixed && op == HELM_OP_L) {
             const zd s(dh, -1.0);
@@ -422,7 +432,13 @@ Vec<const V> cst(Vec<V> v) {
 
 // 3D levels run the fused z-marching passes (kernels3d_fused.hip) unless
 // switched off (no_stream: one thread per node and the column-tile kernel)
-inline bool fused3d(const helm_t* h) { return h->dim == 3 && !h->opts.no_stream; }
+inline bool fused3d(const helm_t* h) { return h->dim == 3 && !h->opts.no_stream && h->dir == 0; }
+
+// Clear the Dirichlet faces of level l in Y (no launch without Dirichlet faces).
+template <typename T>
+void dir_mask(const helm_t* h, hipStream_t st, int l, Vec<cx<T>> Y, int ns) {
+    if (h->dir) mask_faces<T>(st, h->dim, h->nl[l], h->dir, Y, ns);
+}
 
 // Op x (MODE_APPLY), s (b - Op x) (MODE_RESID), a Jacobi sweep (MODE_JACOBI)
 // or the zero-guess sweep (MODE_JACOBI0) on 3D level l, for operator cf
@@ -453,13 +469,21 @@ void apply_mode(helm_t* h, int op, int l, int mode, T s, Vec<const cx<T>> X, Vec
     } else {
         op3d<T, T>(h, h->stream, cf, l, mode, s, X, B, Y, ns);
     }
+    dir_mask<T>(h, h->stream, l, Y, ns);
 }
 
 template <typename T>
 void resid_restrict(helm_t* h, int l, Vec<const cx<T>> X, Vec<const cx<T>> B, Vec<cx<T>> Bc,
                     Vec<cx<T>> tmp, int ns) {
     const Coef cf = h->coef(HELM_OP_L);
-    if (h->dim == 2) {
+    if (h->dir) {
+        // the residual on the face nodes is not part of the system: cleared
+        // before it is restricted, and the coarse face nodes after
+        apply_mode<T>(h, HELM_OP_L, l, MODE_RESID, (T)1, X, B, tmp, ns);
+        if (h->dim == 2) restrict2d<T>(h->stream, h->nl[l], cst(tmp), Bc, ns);
+        else restrict3d<T>(h->stream, h->nl[l], cst(tmp), Bc, ns);
+        dir_mask<T>(h, h->stream, l + 1, Bc, ns);
+    } else if (h->dim == 2) {
         resid_restrict2d<T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
     } else if (fused3d(h)) {
         rr3d<T>(h->stream, make_op3f<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
@@ -474,6 +498,7 @@ template <typename T>
 void prolong(helm_t* h, int l, Vec<const cx<T>> E, Vec<cx<T>> X, int ns) {
     if (h->dim == 2) prolong2d<T>(h->stream, h->nl[l], E, X, ns);
     else prolong3d<T>(h->stream, h->nl[l], E, X, ns);
+    dir_mask<T>(h, h->stream, l, X, ns);
 }
 
 // One V(2,2) cycle on level l for L x = b, starting from x = 0 or (guess)
@@ -531,7 +556,7 @@ void zero(hipStream_t st, cx<T>* p, long long n) {
 // inverse (at most 289 nodes).
 template <typename T>
 int small_start(const helm_t* h) {
-    if (h->dim != 2 || h->levels < 2 || h->nc > 289 || h->opts.no_small) return -1;
+    if (h->dim != 2 || h->levels < 2 || h->nc > 289 || h->opts.no_small || h->dir) return -1;
     for (int l = 1; l < h->levels - 1; ++l) {
         // shared scratch sized for level l and the coarse-solve partials
         size_t elems = std::max((size_t)h->Nl[l], 1024 * sizeof(cxd) / sizeof(cx<T>)) + 1;
@@ -570,7 +595,7 @@ void run_small(helm_t* h, int l0, Vec<const cx<T>> b, Vec<cx<T>> x, int ns) {
 // Levels that run with the register-streaming kernels: every 2D level
 // above the small-level kernel, unless switched off.
 inline bool use_stream(const helm_t* h, int l) {
-    return h->dim == 2 && !h->opts.no_stream && h->nl[l] >= 16;
+    return h->dim == 2 && !h->opts.no_stream && h->nl[l] >= 16 && h->dir == 0;
 }
 
 // Fused 2D cycle from a zero initial guess on level l (l >= 1 inside the HSS
@@ -668,9 +693,11 @@ void hss_step2d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     }
 }
 
-// One shifted-HSS step s in 3D: rho = c (R - B u), q V-cycles, u += e.
+// One shifted-HSS step s with one pass per launch (3D without the fused
+// passes, and every mesh with Dirichlet faces): rho = c (R - B u), q V-cycles,
+// u += e.
 template <typename T>
-void hss_step3d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
+void hss_step_generic(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     const long long N = h->Nl[0];
     Vec<cx<T>> R = at_ws<cx<T>>(ws, Lw.R, N);
     Vec<cx<T>> u = at_ws<cx<T>>(ws, Lw.u, N);
@@ -833,9 +860,10 @@ void hss_step(helm_t* h, const Layout& L, void* ws, int ns, int s) {
             return;
         }
     }
-    if (h->dim == 2) hss_step2d<T>(h, L, ws, ns, s);
+    if (h->dir) hss_step_generic<T>(h, L, ws, ns, s);
+    else if (h->dim == 2) hss_step2d<T>(h, L, ws, ns, s);
     else if (fused3d(h) && h->levels > 1) hss_step3d_fused<T>(h, L, ws, ns, s);
-    else hss_step3d<T>(h, L, ws, ns, s);
+    else hss_step_generic<T>(h, L, ws, ns, s);
 }
 
 // A range of slots that runs its HSS loop on a stream of its own: the
@@ -914,6 +942,7 @@ void ensure_cycles(helm_t* h, const Layout& Lw, void* ws) {
         init[q] = mk((T)re, (T)im);
     }
     HIPCHK(hipMemcpyAsync(e.base, init.data(), sizeof(cx<T>) * N, hipMemcpyHostToDevice, h->stream));
+    dir_mask<T>(h, h->stream, 0, e, 1);
     const int iters = 8;
     std::vector<double> norms;
     for (int it = 0; it < iters; ++it) {
@@ -1072,7 +1101,7 @@ void vcycle_entry(helm_t* h, const Layout& Lw, void* ws, const void* b, void* x,
             return;
         }
     }
-    if (h->dim == 2 || fused3d(h)) {
+    if ((h->dim == 2 && !h->dir) || fused3d(h)) {
         Vec<cx<T>> r = h->dim == 2 ? vcycle2d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns)
                                    : vcycle3d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns);
         if (r.base != xv.base) copy_cast<T, T>(h->stream, N, cst(r), xv, ns);
@@ -1241,6 +1270,7 @@ int richardson_columns(helm_t* h, const cxd* rhs, cxd* x, int nrhs, double tol, 
                                       Br, Rr, nr);
         else
             op3d<double, double>(h, s, b0, 0, MODE_RESID, 1.0, Xr, Br, Rr, nr);
+        if (!h->mixed) dir_mask<double>(h, s, 0, Rr, nr);
         norm2(s, N, cst(Rr), d_npart, d_norm, 1, nr);
         HIPCHK(hipMemcpyAsync(hn, d_norm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1359,6 +1389,7 @@ void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>>
                                  ns);
         else
             op3d<double, T>(h, s, cb, 0, MODE_RESID, 1.0, u, vv, rv, ns);
+        if (!h->mixed) dir_mask<double>(h, s, 0, rv, ns);
         norm2(s, N, cst(rv), d_npart, d_norm, 1, ns);
         HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1449,7 +1480,10 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
     if (o.cycle != HELM_CYCLE_V_JACOBI && o.cycle != HELM_CYCLE_W_GMRES) return HELM_EINVAL;
     if (o.smooth_its < 0 || o.smooth_its > 20) return HELM_EINVAL;
     const bool wvar = o.cycle == HELM_CYCLE_W_GMRES;
-    if (bc && bc->dirichlet_faces != 0) return HELM_ENOTSUP;
+    const unsigned dirm = bc ? bc->dirichlet_faces : 0u;
+    if (dirm & ~((1u << (2 * mesh->dim)) - 1u)) return HELM_EINVAL;
+    // Dirichlet faces: primal form with V cycles only
+    if (dirm && (mixed || wvar)) return HELM_ENOTSUP;
     if (!wvar && (o.nu1 != 2 || o.nu2 != 2)) return HELM_ENOTSUP;
     if (wvar && o.precision != HELM_FP64) return HELM_ENOTSUP;
     // the mixed formulation: V cycles
@@ -1494,6 +1528,7 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
             h->Nl.push_back(Nl);
         }
         h->mixed = mixed;
+        h->dir = dirm;
         h->nv = h->Nl[0] + (mixed ? 4LL * h->n * h->n : 0);
         // coarsest-mesh dense L (from the same stencil rows the kernels use);
         // the W variant smooths on the coarsest mesh instead
@@ -1536,6 +1571,23 @@ int helm_create(const helm_mesh* mesh, double k, double delta, double delta_hat,
                                         zd(w.x, w.y);
                                 }
                     }
+        }
+        // Dirichlet nodes: identity rows and columns (not unknowns)
+        if (h->dir) {
+            const int np = ncs + 1;
+            for (int q = 0; q < nc; ++q) {
+                const int c[3] = {q % np, (q / np) % np, q / (np * np)};
+                bool on = false;
+                for (int ax = 0; ax < h->dim; ++ax)
+                    on = on || (c[ax] == 0 && ((h->dir >> (2 * ax)) & 1u)) ||
+                         (c[ax] == ncs && ((h->dir >> (2 * ax + 1)) & 1u));
+                if (!on) continue;
+                for (int r = 0; r < nc; ++r) {
+                    A[(size_t)q * nc + r] = zd(0.0);
+                    A[(size_t)r * nc + q] = zd(0.0);
+                }
+                A[(size_t)q * nc + q] = zd(1.0);
+            }
         }
         if (!invert_dense(A, nc)) {
             g_last_error = "singular coarsest-mesh operator";
@@ -1752,7 +1804,7 @@ template <typename T>
 static void restrict_t(helm_t* h, int level, const void* x, const void* b, void* bc, int nrhs) {
     const long long N = h->Nl[level], Nc = h->Nl[level + 1];
     cx<T>* tmp = nullptr;
-    if (h->dim == 3)
+    if (h->dim == 3 || h->dir)
         HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(cx<T>) * N * nrhs, h->stream));
     resid_restrict<T>(h, level, Vec<const cx<T>>{static_cast<const cx<T>*>(x), N, 0, nullptr},
                       Vec<const cx<T>>{static_cast<const cx<T>*>(b), N, 0, nullptr},
@@ -1801,14 +1853,18 @@ int helm_coarse_solve(helm_t* h, int prec, const void* b, void* x, int nrhs) {
     if (!h->d_cinv) return HELM_ENOTSUP;  // the W variant has no coarse factorisation
     const long long Nc = h->Nl.back();
     try {
-        if (prec == HELM_FP64)
+        const int lc = h->levels - 1;
+        if (prec == HELM_FP64) {
+            Vec<cxd> xv{static_cast<cxd*>(x), Nc, 0, nullptr};
             coarse_apply<double>(h->stream, h->d_cinv, h->nc,
-                                 Vec<const cxd>{static_cast<const cxd*>(b), Nc, 0, nullptr},
-                                 Vec<cxd>{static_cast<cxd*>(x), Nc, 0, nullptr}, nrhs);
-        else
+                                 Vec<const cxd>{static_cast<const cxd*>(b), Nc, 0, nullptr}, xv, nrhs);
+            dir_mask<double>(h, h->stream, lc, xv, nrhs);
+        } else {
+            Vec<cxf> xv{static_cast<cxf*>(x), Nc, 0, nullptr};
             coarse_apply<float>(h->stream, h->d_cinv, h->nc,
-                                Vec<const cxf>{static_cast<const cxf*>(b), Nc, 0, nullptr},
-                                Vec<cxf>{static_cast<cxf*>(x), Nc, 0, nullptr}, nrhs);
+                                Vec<const cxf>{static_cast<const cxf*>(b), Nc, 0, nullptr}, xv, nrhs);
+            dir_mask<float>(h, h->stream, lc, xv, nrhs);
+        }
         HIPCHK(hipGetLastError());
     } catch (const DevErr&) {
         return HELM_EDEVICE;

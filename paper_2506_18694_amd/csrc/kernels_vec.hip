@@ -3,6 +3,7 @@
 // wavefront shuffles), basis updates, norms, precision casts, and the dense
 // FP64 coarsest-mesh solve.
 #include "launch.h"
+#include "faces.h"
 
 namespace helm {
 
@@ -72,6 +73,24 @@ __global__ __launch_bounds__(BS) void k_copy_cast(long long N, Vec<const cx<TI>>
     const long long t = (long long)(blockIdx.x % gx) * BS + threadIdx.x;
     if (t >= N) return;
     Y.at(slot)[t] = cvt<TO>(X.at(slot)[t]);
+}
+
+// Zero the nodes of the Dirichlet faces (bit f of mask: face f = 2 axis + side,
+// x0 x1 y0 y1 z0 z1).  Block row y is the face, z the slot; x runs over the
+// (n+1)^(dim-1) nodes of the face.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_mask_faces(int dim, int n, unsigned mask, Vec<cx<T>> Y) {
+    const int f = (int)blockIdx.y;
+    if (!((mask >> f) & 1u)) return;
+    const long long n1 = n + 1;
+    const long long m = (long long)blockIdx.x * BS + threadIdx.x;
+    if (m >= (dim == 2 ? n1 : n1 * n1)) return;
+    const int axis = f >> 1;
+    const long long fixed = (f & 1) ? n : 0, a = m % n1, b = m / n1;
+    const long long i = axis == 0 ? fixed : a;
+    const long long j = axis == 1 ? fixed : (axis == 0 ? a : b);
+    const long long l = axis == 2 ? fixed : b;
+    Y.at((int)blockIdx.z)[i + n1 * (j + n1 * l)] = mk((T)0, (T)0);
 }
 
 template <typename T>
@@ -342,6 +361,14 @@ void copy_cast(hipStream_t st, long long N, Vec<const cx<TI>> X, Vec<cx<TO>> Y, 
 }
 
 template <typename T>
+void mask_faces(hipStream_t st, int dim, int n, unsigned mask, Vec<cx<T>> Y, int nslots) {
+    if (mask == 0 || nslots < 1) return;
+    const long long per = dim == 2 ? (long long)(n + 1) : (long long)(n + 1) * (n + 1);
+    const dim3 grid(blocks(per), 2 * dim, nslots);
+    k_mask_faces<T><<<grid, BS, 0, st>>>(dim, n, mask, Y);
+}
+
+template <typename T>
 void axpy1(hipStream_t st, long long N, T alpha, Vec<const cx<T>> X, Vec<cx<T>> Y, int nslots) {
     const unsigned gx = blocks(N);
     k_axpy1<T><<<gx * nslots, BS, 0, st>>>(N, alpha, X, Y, gx);
@@ -405,6 +432,8 @@ template void copy_cast<double, double>(hipStream_t, long long, Vec<const cxd>, 
 template void copy_cast<float, double>(hipStream_t, long long, Vec<const cxd>, Vec<cxf>, int);
 template void copy_cast<double, float>(hipStream_t, long long, Vec<const cxf>, Vec<cxd>, int);
 template void copy_cast<float, float>(hipStream_t, long long, Vec<const cxf>, Vec<cxf>, int);
+template void mask_faces<double>(hipStream_t, int, int, unsigned, Vec<cxd>, int);
+template void mask_faces<float>(hipStream_t, int, int, unsigned, Vec<cxf>, int);
 template void axpy1<double>(hipStream_t, long long, double, Vec<const cxd>, Vec<cxd>, int);
 template void axpy1<float>(hipStream_t, long long, float, Vec<const cxf>, Vec<cxf>, int);
 template void update_solution<double>(hipStream_t, long long, int, const int*, Vec<const cxd>,

@@ -90,7 +90,13 @@ def test_create_rejects_bad_options_and_unsupported():
     L.helm_opts_default(ctypes.byref(o))
     o.nu1 = 3
     assert _create(helm, L, opts=o)[0] == helm.HELM_ENOTSUP
-    assert _create(helm, L, bc=helm.helm_bc(1))[0] == helm.HELM_ENOTSUP
+    # Dirichlet faces: bits beyond the 2 dim faces, the mixed element, W cycles
+    assert _create(helm, L, bc=helm.helm_bc(16))[0] == helm.HELM_EINVAL
+    assert _create(helm, L, dim=3, elem=helm.HELM_Q1_HEX, bc=helm.helm_bc(64))[0] == helm.HELM_EINVAL
+    assert _create(helm, L, elem=helm.HELM_MIXED_DG0_P1, bc=helm.helm_bc(1))[0] == helm.HELM_ENOTSUP
+    L.helm_opts_default(ctypes.byref(o))
+    o.cycle = helm.HELM_CYCLE_W_GMRES
+    assert _create(helm, L, opts=o, bc=helm.helm_bc(3))[0] == helm.HELM_ENOTSUP
     assert L.helm_create(None, 1.0, 0.0, 1.0, None, None, None, None) == helm.HELM_EINVAL
 
 
