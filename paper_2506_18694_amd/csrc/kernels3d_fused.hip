@@ -220,7 +220,7 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
     constexpr int OWN = LW - 2 * NS, OWNH = LH - 2 * NS;  // owned columns and rows of a tile
     static_assert(!(PRO && PW), "the prolongation feeds a stencil first stage");
     __shared__ cx<T> pin[2][LH][LW];
-    __shared__ cx<T> pmid[LH][LW];
+    __shared__ cx<T> pmid[NS == 2 ? 2 : 1][LH][LW];
     __shared__ cx<T> cpl[PRO ? 2 : 1][PRO ? CWH : 1][PRO ? CW : 1];
     int slot, tx, ty, seg;
     unit_of(g, slot, tx, ty, seg);
@@ -284,9 +284,12 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
     const int o0 = z0 - (NS - 1), o1 = z1 + (NS - 1);
     int p0 = PW ? o0 : o0 - 1;
     if (PRO) p0 -= p0 & 1;  // an even first plane (its output is not stored)
-    const int p1 = PW ? o1 - 1 : o1;
+    // the second stage runs two planes behind the first (it reads the
+    // middle plane the first stage wrote at the previous step), so the
+    // march takes one step more
+    const int p1 = (PW ? o1 - 1 : o1) + (NS == 2 ? 1 : 0);
     const int qb = PW ? p0 : p0 - 1;  // plane the first stage outputs at step p0
-    const int qy = NS == 1 ? qb : qb - 1;  // plane the last stage outputs at step p0
+    const int qy = NS == 1 ? qb : qb - 2;  // plane the last stage outputs at step p0
     // rings: x at planes p + 1 .. p + PF, b at q1 .. q1 + PF - 1 and y at the
     // output planes of steps p .. p + PF - 1 (step p0 + u uses slot u % PF)
     cx<TI> xr[PF];
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
     // stage 1: acc1 = T1(q - 1) + T0(q) for the next output plane q, T1p = T1(q);
     // xc: input centre of q.  Stage 2 likewise, with b2 its right-hand side.
     cx<T> acc1 = z, T1p = z, xc = z;
-    cx<T> acc2 = z, U1p = z, xc2 = z, b2 = z;
+    cx<T> acc2 = z, U1p = z, xc2 = z, b2 = z, b2n = z;
 
     auto step = [&](auto uc, int p) __attribute__((always_inline)) {
         constexpr int u = decltype(uc)::value;
@@ -401,10 +404,12 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
             }
             return;
         }
-        // second stage: x1 of plane q1 through the middle plane; output q1 - 1
-        pmid[ly][lx] = x1;
-        __syncthreads();
-        const int q2 = q1 - 1;
+        // second stage: x1 of plane q1 - 1, written to the middle plane at
+        // the previous step (ordered by this step's barrier); output q1 - 2.
+        // x1 of plane q1 goes to the other middle buffer, read at the next
+        // step, so one barrier per step orders both.
+        pmid[kb][ly][lx] = x1;
+        const int qm = q1 - 1, q2 = q1 - 2;
         cx<T> yo = z;
         if (UPD == 1) {
             yo = yr[sl];
@@ -412,9 +417,9 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
         }
         if (st2) {
             cx<T> a0, H, V, a2, u1 = z, u0 = z;
-            plane_sums<T>(pmid, ly, lx, a0, H, V, a2);
-            if (q1 >= 0 && q1 <= n)
-                plane_terms<T>(L, edge_wave, a0, H, V, a2, bx, by, (q1 == 0) | (q1 == n), u1, u0);
+            plane_sums<T>(pmid[kb ^ 1], ly, lx, a0, H, V, a2);
+            if (qm >= 0 && qm <= n)
+                plane_terms<T>(L, edge_wave, a0, H, V, a2, bx, by, (qm == 0) | (qm == n), u1, u0);
             if (owned && q2 >= z0 && q2 < z1) {
                 const cx<T> od2 = odf(q2);
                 const cx<T> x2 = cfma(od2, b2 - (acc2 + u1), xc2);
@@ -423,8 +428,9 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
             acc2 = U1p + u0;
             U1p = u1;
             xc2 = a0;
-            b2 = bq;
         }
+        b2 = b2n;
+        b2n = bq;
     };
     int pb = p0;
     for (; pb + UNR - 1 <= p1; pb += UNR) {
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>>
     __shared__ cx<T> pin[2][LH][LW];
     // residual plane with the even and odd columns of a row stored apart, so
     // that the coarse columns of the second stage read consecutive words
-    __shared__ cx<T> pres[LH][2][LW / 2];
+    __shared__ cx<T> pres[2][LH][2][LW / 2];
     int slot, tx, ty, seg;
     unit_of(g, slot, tx, ty, seg);
     const int n = L.n, nc = n / 2;
@@ -527,20 +533,23 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>>
         if (st1 && inmesh && q >= 0 && q <= n) r = bcur - (acc + t1);
         acc = T1p + t0;
         T1p = t1;
-        pres[ly][lx & 1][lx >> 1] = r;
-        __syncthreads();
+        pres[kb][ly][lx & 1][lx >> 1] = r;
+        // second stage on the residual plane q - 1, written at the previous
+        // step into the other buffer (ordered by this step's barrier)
         if (cst) {
+            const cx<T>(*pr)[2][LW / 2] = pres[kb ^ 1];
             cx<T> c0, cH, cV, c2;
             // fine centre (2 cj + 2, 2 ci + 2): even column ci + 1, its
             // neighbours the odd columns ci and ci + 1 of the same rows
             const int r0 = 2 * cj + 2;
-            c0 = pres[r0][0][ci + 1];
-            cH = pres[r0][1][ci] + pres[r0][1][ci + 1];
-            cV = pres[r0 - 1][0][ci + 1] + pres[r0 + 1][0][ci + 1];
-            c2 = (pres[r0 - 1][1][ci] + pres[r0 - 1][1][ci + 1]) + (pres[r0 + 1][1][ci] + pres[r0 + 1][1][ci + 1]);
+            c0 = pr[r0][0][ci + 1];
+            cH = pr[r0][1][ci] + pr[r0][1][ci + 1];
+            cV = pr[r0 - 1][0][ci + 1] + pr[r0 + 1][0][ci + 1];
+            c2 = (pr[r0 - 1][1][ci] + pr[r0 - 1][1][ci + 1]) + (pr[r0 + 1][1][ci] + pr[r0 + 1][1][ci + 1]);
             const cx<T> r2 = c0 + (T)0.5 * (cH + cV) + (T)0.25 * c2;
-            if (kb == 0) {  // q odd
-                const int Lc = (q - 1) >> 1;  // coarse plane completed by this odd plane
+            const int q2 = q - 1;  // same parity as p
+            if (kb == 1) {  // q2 odd
+                const int Lc = (q2 - 1) >> 1;  // coarse plane completed by this odd plane
                 if (cown && Lc >= Z0 && Lc < Z1) sto(bc + (long long)Lc * szc, occ, cur + (T)0.5 * r2);
                 half = (T)0.5 * r2;
             } else {
@@ -548,8 +557,11 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>>
             }
         }
     };
+    // the restriction of the last residual plane (2 Z1 - 1) runs one step
+    // after it is formed
+    const int pe = p1 + 1;
     int pb = p0;
-    for (; pb + UNR - 1 <= p1; pb += UNR) {
+    for (; pb + UNR - 1 <= pe; pb += UNR) {
         step(IC<0>{}, pb);
         step(IC<1>{}, pb + 1);
         step(IC<2>{}, pb + 2);
@@ -557,11 +569,11 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>>
         step(IC<4>{}, pb + 4);
         step(IC<5>{}, pb + 5);
     }
-    if (pb <= p1) step(IC<0>{}, pb);
-    if (pb + 1 <= p1) step(IC<1>{}, pb + 1);
-    if (pb + 2 <= p1) step(IC<2>{}, pb + 2);
-    if (pb + 3 <= p1) step(IC<3>{}, pb + 3);
-    if (pb + 4 <= p1) step(IC<4>{}, pb + 4);
+    if (pb <= pe) step(IC<0>{}, pb);
+    if (pb + 1 <= pe) step(IC<1>{}, pb + 1);
+    if (pb + 2 <= pe) step(IC<2>{}, pb + 2);
+    if (pb + 3 <= pe) step(IC<3>{}, pb + 3);
+    if (pb + 4 <= pe) step(IC<4>{}, pb + 4);
 }
 
 // Workgroups of a kernel that the device holds at once (its occupancy per
