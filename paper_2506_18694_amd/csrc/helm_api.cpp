@@ -747,6 +747,17 @@ void sweeps3d(helm_t* h, const Op3F<T>& L, const Op3F<T>& B, int first, bool pro
               Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho,
               Vec<cx<T>> Tmp, Vec<cx<T>> Y, int ns, bool two, bool prof = false, double bytes = 0.0) {
     if (prof) h->prof_mark();
+    if (!two && first == F_PRE0 && !pro && upd == 0) {
+        // both zero-guess sweeps in one stencil pass (the first formed on
+        // the staged input planes)
+        STREAMCHK((pass3d<T, T>(h->stream, L, L, F_JAC0, 1, false, 0, (T)1, Vec<const cx<T>>{}, Bv,
+                                Vec<const cx<T>>{}, Vec<cx<T>>{}, Y, ns)));
+        if (prof) {
+            h->prof_mark();
+            h->prof_pending_bytes += sizeof(cx<T>) * (double)ns * bytes;
+        }
+        return;
+    }
     if (two) {
         STREAMCHK((pass3d<T, T>(h->stream, L, B, first, 2, pro, upd, s, X, Bv, Ec, Rho, Y, ns)));
     } else {

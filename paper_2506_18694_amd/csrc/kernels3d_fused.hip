@@ -199,6 +199,8 @@ using IC = std::integral_constant<int, U>;
 //            second operator, R in Bv, u in X
 //   F_HSS0   rho = s R (written), x1 = w/D rho   (u = 0; pointwise)
 //   F_PRE0   x1 = w/D b                          (pointwise)
+//   F_JAC0   x1 = x0 + w/D (b - L x0) with x0 = w/D b: the two zero-guess
+//            sweeps, the first formed on each input plane as it is staged
 // NS = 2 adds x2 = x1 + w/D (b - L x1) (b = rho for the HSS forms).
 // UPD: 0 y = result, 1 y += result (the HSS update u += e with u in Y).
 //
@@ -248,7 +250,8 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
     const unsigned ox = (unsigned)col * (unsigned)sizeof(cx<TI>), ob = (unsigned)col * (unsigned)sizeof(cx<T>);
     const int z0 = seg * g.tz, z1 = min(z0 + g.tz, n + 1);  // output planes [z0, z1)
     // vector bases (plane l at + l sz)
-    const cx<TI>* xs = X.base ? X.at(slot) : nullptr;
+    constexpr bool J0 = FIRST == F_JAC0;
+    const cx<TI>* xs = J0 ? reinterpret_cast<const cx<TI>*>(Bv.at(slot)) : (X.base ? X.at(slot) : nullptr);
     const cx<T>* bs = Bv.base ? Bv.at(slot) : nullptr;
     cx<T>* rs = HSS ? Rho.at(slot) : nullptr;
     cx<T>* ys = Y.at(slot);
@@ -307,6 +310,7 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
     }
     if (!PW) {
         cx<T> v = cvt<T>(ldx(p0, p1));
+        if (J0) v = odf(p0) * v;
         if (PRO) v = v + (T)0.25 * cB;
         pin[0][ly][lx] = csel(lok(p0), v, z);
     }
@@ -332,6 +336,7 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
             // input plane p + 1 into the buffer of plane p - 1 (free since the
             // barrier; past the last plane it is written and never read)
             cx<T> v = cvt<T>(xr[sl]);
+            if (J0) v = odf(p + 1) * v;
             if (PRO) {
                 if (kb == 0) {  // p + 1 = 2C - 1
                     cA = cB;
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
                     x1 = ax;
                 } else if (FIRST == F_RESID) {
                     x1 = s * (bcur - ax);
-                } else if (FIRST == F_JAC) {
+                } else if (FIRST == F_JAC || J0) {
                     x1 = cfma(od1, bcur - ax, xc);
                     bq = bcur;
                 } else {  // F_HSS
@@ -597,7 +602,7 @@ int resident_units() {
 // rounds x (planes + HEAD), at least MINTZ planes unless one segment
 // covers the level.
 #ifndef HELM_K3_MINTZ
-#define HELM_K3_MINTZ 2
+#define HELM_K3_MINTZ 1
 #endif
 #ifndef HELM_K3_HEAD
 #define HELM_K3_HEAD 4
@@ -681,6 +686,7 @@ bool pass3d(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, int first, int n
             if (first == F_JAC && !pro && upd == 1) HELM_P3(F_JAC, 1, false, 1);
             if (first == F_HSS && !pro && upd == 0) HELM_P3(F_HSS, 1, false, 0);
             if (first == F_HSS0 && !pro && upd == 0) HELM_P3(F_HSS0, 1, false, 0);
+            if (first == F_JAC0 && !pro && upd == 0) HELM_P3(F_JAC0, 1, false, 0);
         }
         if (ns == 2) {
             if (first == F_JAC && !pro && upd == 0) HELM_P3(F_JAC, 2, false, 0);

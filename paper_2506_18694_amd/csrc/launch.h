@@ -140,11 +140,13 @@ enum Pass3First : int {
     F_HSS = 3,    // rho = s (R - B u), x1 = w/D rho
     F_HSS0 = 4,   // rho = s R, x1 = w/D rho
     F_PRE0 = 5,   // x1 = w/D b
+    F_JAC0 = 6,   // x1 = x0 + w/D (b - L x0), x0 = w/D b: both zero-guess sweeps
 };
 // One fused pass: the first stage, and with ns = 2 a Jacobi sweep on its
 // output (b = rho for the HSS forms).  Supported: ns = 1 with F_APPLY,
 // F_RESID, F_JAC, F_PRE0 (any TI), and (TI = T) F_JAC with pro (the input
-// is X + P Ec) or upd = 1 (Y += result), F_HSS, F_HSS0; ns = 2 (TI = T)
+// is X + P Ec) or upd = 1 (Y += result), F_HSS, F_HSS0, F_JAC0 (X unused:
+// the input planes are w/D b, formed from Bv); ns = 2 (TI = T)
 // with F_JAC (pro, upd as before), F_HSS, F_HSS0, F_PRE0.  X, Bv,
 // Ec, Rho, Y as the form needs; Y must not alias X.  tz: planes per
 // segment (0 = from the launch shape).  Returns false (and launches
