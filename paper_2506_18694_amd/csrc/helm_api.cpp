@@ -736,6 +736,9 @@ void hss_step_generic(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
 #ifndef HELM_K3_TWO_STAGE_FP64
 #define HELM_K3_TWO_STAGE_FP64 0
 #endif
+#ifndef HELM_K3_PAIR_PRE_FP64
+#define HELM_K3_PAIR_PRE_FP64 0
+#endif
 template <typename T>
 constexpr bool two_stage3d(bool coarse) {
     return sizeof(T) == 4 ? HELM_K3_TWO_STAGE_FP32 != 0
@@ -826,13 +829,24 @@ void hss_step3d_fused(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     // the one-stage (FP64) sequence keeps the cycle's iterate in x, with t
     // between its two sweeps; the two-stage (FP32) one alternates x and t
     const bool two = two_stage3d<T>(false), one = !two;
-    if (s == 0) sweeps3d<T>(h, L, Bs, F_HSS0, false, 0, c, none, cst(R), none, rho, t, x, ns, two);
-    else sweeps3d<T>(h, L, Bs, F_HSS, false, 0, c, cst(u), cst(R), none, rho, t, x, ns, two);
+    if (s == 0) {
+        sweeps3d<T>(h, L, Bs, F_HSS0, false, 0, c, none, cst(R), none, rho, t, x, ns, two);
+    } else if (one) {
+        // rho = c (R - B u) in one pass, then both zero-guess sweeps on rho
+        // in the next (five vectors moved instead of seven)
+        STREAMCHK((pass3d<T, T>(h->stream, Bs, Bs, F_RESID, 1, false, 0, c, cst(u), cst(R), none,
+                                Vec<cx<T>>{}, rho, ns)));
+        sweeps3d<T>(h, L, L, F_PRE0, false, 0, (T)1, none, cst(rho), none, Vec<cx<T>>{}, t, x, ns, false);
+    } else {
+        sweeps3d<T>(h, L, Bs, F_HSS, false, 0, c, cst(u), cst(R), none, rho, t, x, ns, two);
+    }
     for (int q = 0; q < h->cycles; ++q) {
         if (q > 0) {
+            // the pre-smoothing pair from the previous result
+            const bool pair = two || HELM_K3_PAIR_PRE_FP64 != 0;
             sweeps3d<T>(h, L, L, F_JAC, false, 0, (T)1, cst(x), cst(rho), none, Vec<cx<T>>{}, t,
-                        one ? x : t, ns, two);
-            if (!one) std::swap(x, t);
+                        pair ? t : x, ns, pair);
+            if (pair) std::swap(x, t);
         }
         rr3d<T>(h->stream, L, cst(x), cst(rho), b1, ns);
         Vec<const cx<T>> ec = cst(vcycle3d_zero<T>(h, Lw, ws, 1, cst(b1), x1, t1, ns));
