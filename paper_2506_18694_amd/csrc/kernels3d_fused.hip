@@ -49,26 +49,40 @@ namespace {
 // (one value per thread); the first stage runs on its interior
 // (LW - 2) x (H - 2) columns, the second stage on the (LW - 4) x (H - 4)
 // inside that.
-// Tile rows by precision: FP64 tiles are 32 x 32 (1024 threads; its passes
-// are bound by HBM, so the smallest halo share wins), FP32 tiles 32 x 16
-// (512 threads: its passes are bound by issue and the two barriers per
-// plane, and two 512-thread workgroups per CU overlap each other's
-// barriers).
+// Tile rows by precision and level: FP64 tiles on the fine levels are
+// 32 x 32 (1024 threads; those passes are bound by HBM, so the smallest
+// halo share wins), FP32 tiles 32 x 16 (512 threads: its passes are bound
+// by issue and the barrier per plane, and two 512-thread workgroups per CU
+// overlap each other's barriers).
 #ifndef HELM_K3_LH_FP64
 #define HELM_K3_LH_FP64 32
 #endif
 #ifndef HELM_K3_LH_FP32
 #define HELM_K3_LH_FP32 16
 #endif
+// The latency-bound coarse FP64 levels use 32 x 16 tiles as well: twice the
+// workgroups, two per CU.
+#ifndef HELM_K3_LH_FP64_COARSE
+#define HELM_K3_LH_FP64_COARSE 16
+#endif
+// levels with at least this many cells per side use the full-height tile
+#ifndef HELM_K3_TALL_N
+#define HELM_K3_TALL_N 192
+#endif
 constexpr int LW = 32;            // tile columns (x)
 constexpr int RC = (LW - 4) / 2;  // coarse columns per tile in the restriction
-template <typename T>
+template <int LH>
 struct Tile {
-    static constexpr int H = sizeof(T) == 4 ? HELM_K3_LH_FP32 : HELM_K3_LH_FP64;  // tile rows (y)
+    static constexpr int H = LH;                // tile rows (y)
     static constexpr int FT = LW * H;           // threads per workgroup
     static constexpr int RCH = (H - 4) / 2;     // coarse rows per tile in the restriction
     static constexpr int CWH = H / 2 + 1;       // coarse rows under a tile (prolongation)
 };
+// tile rows of a level of n cells per side
+template <typename T>
+constexpr int tall_rows() { return sizeof(T) == 4 ? HELM_K3_LH_FP32 : HELM_K3_LH_FP64; }
+template <typename T>
+constexpr int short_rows() { return sizeof(T) == 4 ? HELM_K3_LH_FP32 : HELM_K3_LH_FP64_COARSE; }
 #ifndef HELM_K3_PF
 #define HELM_K3_PF 2
 #endif
@@ -212,13 +226,13 @@ using IC = std::integral_constant<int, U>;
 // 2C + 1 takes (ce(C) + ce(C + 1)) / 8 (exact powers of two).  The coarse
 // plane for fine step p is written to LDS one step ahead and requested two
 // steps ahead of that; the march then starts on an even plane.
-template <typename T, typename TI, int FIRST, int NS, bool PRO, int UPD>
-__global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<const cx<TI>> X,
+template <typename T, typename TI, int FIRST, int NS, bool PRO, int UPD, int TH>
+__global__ __launch_bounds__(Tile<TH>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<const cx<TI>> X,
                                               Vec<const cx<T>> Bv, Vec<const cx<T>> Ec,
                                               Vec<cx<T>> Rho, Vec<cx<T>> Y, Grid3F g) {
     constexpr bool PW = FIRST == F_HSS0 || FIRST == F_PRE0;
     constexpr bool HSS = FIRST == F_HSS || FIRST == F_HSS0;
-    constexpr int LH = Tile<T>::H, CWH = Tile<T>::CWH;
+    constexpr int LH = Tile<TH>::H, CWH = Tile<TH>::CWH;
     constexpr int OWN = LW - 2 * NS, OWNH = LH - 2 * NS;  // owned columns and rows of a tile
     static_assert(!(PRO && PW), "the prolongation feeds a stencil first stage");
     __shared__ cx<T> pin[2][LH][LW];
@@ -461,10 +475,10 @@ __global__ __launch_bounds__(Tile<T>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s
 // planes (weight 1 on plane 2 L, 1/2 on 2 L +- 1).  Segments own coarse
 // planes [Z0, Z0 + tz).  The march starts on an even plane and is unrolled
 // as in k3_pass.
-template <typename T>
-__global__ __launch_bounds__(Tile<T>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<const cx<T>> Bv,
+template <typename T, int TH>
+__global__ __launch_bounds__(Tile<TH>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<const cx<T>> Bv,
                                                      Vec<cx<T>> Bc, Grid3F g) {
-    constexpr int LH = Tile<T>::H, RCH = Tile<T>::RCH;
+    constexpr int LH = Tile<TH>::H, RCH = Tile<TH>::RCH;
     __shared__ cx<T> pin[2][LH][LW];
     // residual plane with the even and odd columns of a row stored apart, so
     // that the coarse columns of the second stage read consecutive words
@@ -647,20 +661,48 @@ int seg_planes_rr(int cplanes, int tiles, int nslots, int resident) {
     return best;
 }
 
-template <typename T, typename TI, int F, int NS, bool PRO, int UPD>
-void launch_pass(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
-                 Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
-                 int tz) {
-    const int n = L.n, own = LW - 2 * NS, ownh = Tile<T>::H - 2 * NS;
+template <typename T, typename TI, int F, int NS, bool PRO, int UPD, int TH>
+void launch_pass_h(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
+                   Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
+                   int tz) {
+    const int n = L.n, own = LW - 2 * NS, ownh = Tile<TH>::H - 2 * NS;
     Grid3F g;
     g.tiles_x = (n + 1 + own - 1) / own;
     g.tiles_y = (n + 1 + ownh - 1) / ownh;
     g.tz = tz > 0 ? tz
                   : seg_planes(n + 1, g.tiles_x * g.tiles_y, nslots,
-                               resident_units<k3_pass<T, TI, F, NS, PRO, UPD>, Tile<T>::FT>());
+                               resident_units<k3_pass<T, TI, F, NS, PRO, UPD, TH>, Tile<TH>::FT>());
     g.segs = (n + 1 + g.tz - 1) / g.tz;
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
-    k3_pass<T, TI, F, NS, PRO, UPD><<<grid, Tile<T>::FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g);
+    k3_pass<T, TI, F, NS, PRO, UPD, TH><<<grid, Tile<TH>::FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g);
+}
+
+template <typename T, typename TI, int F, int NS, bool PRO, int UPD>
+void launch_pass(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
+                 Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
+                 int tz) {
+    if constexpr (short_rows<T>() != tall_rows<T>()) {
+        if (L.n < HELM_K3_TALL_N) {
+            launch_pass_h<T, TI, F, NS, PRO, UPD, short_rows<T>()>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
+            return;
+        }
+    }
+    launch_pass_h<T, TI, F, NS, PRO, UPD, tall_rows<T>()>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
+}
+
+template <typename T, int TH>
+void rr3d_h(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<cx<T>> Bc,
+            int nslots, int tz) {
+    const int nc = L.n / 2;
+    Grid3F g;
+    g.tiles_x = (nc + 1 + RC - 1) / RC;
+    g.tiles_y = (nc + 1 + Tile<TH>::RCH - 1) / Tile<TH>::RCH;
+    g.tz = tz > 0 ? tz
+                  : seg_planes_rr(nc + 1, g.tiles_x * g.tiles_y, nslots,
+                                  resident_units<k3_rr<T, TH>, Tile<TH>::FT>());
+    g.segs = (nc + 1 + g.tz - 1) / g.tz;
+    const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
+    k3_rr<T, TH><<<grid, Tile<TH>::FT, 0, st>>>(L, X, Bv, Bc, g);
 }
 
 }  // namespace
@@ -704,15 +746,13 @@ bool pass3d(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, int first, int n
 template <typename T>
 void rr3d(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<cx<T>> Bc,
           int nslots, int tz) {
-    const int nc = L.n / 2;
-    Grid3F g;
-    g.tiles_x = (nc + 1 + RC - 1) / RC;
-    g.tiles_y = (nc + 1 + Tile<T>::RCH - 1) / Tile<T>::RCH;
-    g.tz = tz > 0 ? tz
-                  : seg_planes_rr(nc + 1, g.tiles_x * g.tiles_y, nslots, resident_units<k3_rr<T>, Tile<T>::FT>());
-    g.segs = (nc + 1 + g.tz - 1) / g.tz;
-    const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
-    k3_rr<T><<<grid, Tile<T>::FT, 0, st>>>(L, X, Bv, Bc, g);
+    if constexpr (short_rows<T>() != tall_rows<T>()) {
+        if (L.n < HELM_K3_TALL_N) {
+            rr3d_h<T, short_rows<T>()>(st, L, X, Bv, Bc, nslots, tz);
+            return;
+        }
+    }
+    rr3d_h<T, tall_rows<T>()>(st, L, X, Bv, Bc, nslots, tz);
 }
 
 template bool pass3d<double, double>(hipStream_t, const Op3F<double>&, const Op3F<double>&, int, int,
