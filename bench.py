@@ -27,6 +27,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import platform
@@ -71,11 +72,19 @@ DOMINANT = {
 }
 
 
+def code_tokens(text):
+    """Source text without comments and with whitespace runs collapsed, so
+    that an edit of a comment does not count as a change of the kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash(dim):
     h = hashlib.sha256()
     for f in DOMINANT[dim]["sources"]:
-        with open(os.path.join(ROOT, "paper_2506_18694_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2506_18694_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_tokens(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

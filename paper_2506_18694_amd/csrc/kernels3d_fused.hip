@@ -24,14 +24,16 @@
 // One workgroup owns a tile of mesh columns and a segment of planes and
 // marches up the segment.  Each plane of the input passes once through a
 // double-buffered LDS plane with a one-node halo (the plane after the next
-// already requested), and every dependent pass is a pipeline stage one
-// plane behind the previous one: the first stage's output plane reaches the
-// second stage through a second LDS plane.  Passes:
+// already requested), and every dependent pass is a pipeline stage behind
+// the previous one: the first stage's output plane reaches the second stage
+// through a second double-buffered LDS plane, read at the next step, so that
+// one barrier per step orders every plane exchange.  Passes:
 //   k3_pass  one or two operator stages: apply, scaled residual, Jacobi
 //            sweeps (from a guess, from the guess plus the prolonged coarse
 //            correction, or from zero), the shifted-HSS residual
-//            rho = c (R - B u) with the first zero-guess sweep, and the HSS
-//            update u += x or u = x on the last output
+//            rho = c (R - B u) with the first zero-guess sweep, both
+//            zero-guess sweeps in one stencil stage, and the HSS update
+//            u += x or u = x on the last output
 //   k3_rr    residual restriction b_c = P^T (b - L x): stage 1 forms the
 //            residual plane, stage 2 applies the transpose of trilinear
 //            interpolation (in-plane weights 1, 1/2, 1/4; across planes
