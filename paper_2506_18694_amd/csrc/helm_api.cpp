@@ -156,13 +156,14 @@ Op3<T> make_op3(const Coef& cf, int n, double omega) {
 // K1 = (1/h)[-1 2 -1], M1 = (h/6)[1 4 1] (boundary rows halve the centre)
 // and the Jacobi factors omega / D by the number of boundary coordinates.
 template <typename T>
-Op3F<T> make_op3f(const Coef& cf, int n, double omega) {
+Op3F<T> make_op3f(const Coef& cf, int n, double omega, unsigned dir = 0) {
     const double h = 1.0 / n, h6 = h / 6.0, ih = 1.0 / h;
     const zd a = cf.a, b = cf.b, c = cf.c;
     // T1 = uK PK + uM PMM + uG PG and T0 = vK PK + vM PMM + vG PG
     const zd uK = h6 * a, uM = h6 * b - a * ih, uG = h6 * c;
     const zd vK = 4.0 * h6 * a, vM = 4.0 * h6 * b + 2.0 * a * ih, vG = 4.0 * h6 * c;
     Op3F<T> o;
+    o.dir = dir;
     // interior columns: PK = (16 a0 - 2 (H + V) - 2 a2) / 6 and
     // PMM = (h/6)^2 (16 a0 + 4 (H + V) + a2), PG = 0
     const double pk[3] = {16.0 / 6.0, -2.0 / 6.0, -2.0 / 6.0};
@@ -307,10 +308,11 @@ struct helm_s {
     // Dirichlet faces (u = 0; bit f: x0 x1 y0 y1 z0 z1).  Their nodes are
     // not unknowns: every vector the library produces is zero there, and
     // the operators' rows on the other nodes are those of the Sommerfeld
-    // operator (whose couplings to the face nodes meet zeros).  Such handles
-    // run the one-pass-per-launch path with the faces cleared after every
-    // pass (the fused passes would carry nonzero face values between their
-    // internal sweeps).
+    // operator (whose couplings to the face nodes meet zeros).  The 3D
+    // z-marching passes clear the face nodes of every stage output
+    // themselves; 2D handles run the one-pass-per-launch path with the faces
+    // cleared after every pass (the fused 2D passes would carry nonzero face
+    // values between their internal sweeps).
     unsigned dir = 0;
 
     Coef coef(int op) const {
@@ -432,7 +434,7 @@ Vec<const V> cst(Vec<V> v) {
 
 // 3D levels run the fused z-marching passes (kernels3d_fused.hip) unless
 // switched off (no_stream: one thread per node and the column-tile kernel)
-inline bool fused3d(const helm_t* h) { return h->dim == 3 && !h->opts.no_stream && h->dir == 0; }
+inline bool fused3d(const helm_t* h) { return h->dim == 3 && !h->opts.no_stream; }
 
 // Clear the Dirichlet faces of level l in Y (no launch without Dirichlet faces).
 template <typename T>
@@ -447,7 +449,7 @@ void op3d(helm_t* h, hipStream_t st, const Coef& cf, int l, int mode, T s, Vec<c
           Vec<const cx<T>> B, Vec<cx<T>> Y, int ns) {
     if (fused3d(h) && (mode == MODE_APPLY || mode == MODE_RESID || mode == MODE_JACOBI ||
                        mode == MODE_JACOBI0)) {
-        const Op3F<T> o = make_op3f<T>(cf, h->nl[l], h->omega);
+        const Op3F<T> o = make_op3f<T>(cf, h->nl[l], h->omega, h->dir);
         const int first = mode == MODE_APPLY ? F_APPLY
                           : mode == MODE_RESID ? F_RESID
                           : mode == MODE_JACOBI ? F_JAC
@@ -476,7 +478,10 @@ template <typename T>
 void resid_restrict(helm_t* h, int l, Vec<const cx<T>> X, Vec<const cx<T>> B, Vec<cx<T>> Bc,
                     Vec<cx<T>> tmp, int ns) {
     const Coef cf = h->coef(HELM_OP_L);
-    if (h->dir) {
+    if (fused3d(h)) {
+        // Dirichlet faces are cleared inside the pass
+        rr3d<T>(h->stream, make_op3f<T>(cf, h->nl[l], h->omega, h->dir), X, B, Bc, ns);
+    } else if (h->dir) {
         // the residual on the face nodes is not part of the system: cleared
         // before it is restricted, and the coarse face nodes after
         apply_mode<T>(h, HELM_OP_L, l, MODE_RESID, (T)1, X, B, tmp, ns);
@@ -485,8 +490,6 @@ void resid_restrict(helm_t* h, int l, Vec<const cx<T>> X, Vec<const cx<T>> B, Ve
         dir_mask<T>(h, h->stream, l + 1, Bc, ns);
     } else if (h->dim == 2) {
         resid_restrict2d<T>(h->stream, make_op2<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
-    } else if (fused3d(h)) {
-        rr3d<T>(h->stream, make_op3f<T>(cf, h->nl[l], h->omega), X, B, Bc, ns);
     } else {
         stencil3d<T, T>(h->stream, make_op3<T>(cf, h->nl[l], h->omega), MODE_RESID, (T)1, X, B,
                         tmp, ns, !h->opts.no_stream);
@@ -788,7 +791,7 @@ Vec<cx<T>> vcycle3d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const
         coarse_apply<T>(h->stream, h->d_cinv, h->nc, b, x, ns);
         return x;
     }
-    const Op3F<T> L = make_op3f<T>(h->coef(HELM_OP_L), h->nl[l], h->omega);
+    const Op3F<T> L = make_op3f<T>(h->coef(HELM_OP_L), h->nl[l], h->omega, h->dir);
     const long long Nc = h->Nl[l + 1];
     Vec<cx<T>> bc = at_ws<cx<T>>(ws, Lw.mg_b[l + 1], Nc);
     Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
@@ -823,8 +826,8 @@ void hss_step3d_fused(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     Vec<cx<T>> x1 = at_ws<cx<T>>(ws, Lw.mg_x[1], N1);
     Vec<cx<T>> t1 = at_ws<cx<T>>(ws, Lw.mg_t[1], N1);
     const T c = (T)(2.0 * h->k / (h->k + 1.0));
-    const Op3F<T> L = make_op3f<T>(h->coef(HELM_OP_L), h->nl[0], h->omega);
-    const Op3F<T> Bs = make_op3f<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega);
+    const Op3F<T> L = make_op3f<T>(h->coef(HELM_OP_L), h->nl[0], h->omega, h->dir);
+    const Op3F<T> Bs = make_op3f<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega, h->dir);
     const Vec<const cx<T>> none{};
     // the one-stage (FP64) sequence keeps the cycle's iterate in x, with t
     // between its two sweeps; the two-stage (FP32) one alternates x and t
@@ -885,8 +888,7 @@ void hss_step(helm_t* h, const Layout& L, void* ws, int ns, int s) {
             return;
         }
     }
-    if (h->dir) hss_step_generic<T>(h, L, ws, ns, s);
-    else if (h->dim == 2) hss_step2d<T>(h, L, ws, ns, s);
+    if (h->dim == 2 && !h->dir) hss_step2d<T>(h, L, ws, ns, s);
     else if (fused3d(h) && h->levels > 1) hss_step3d_fused<T>(h, L, ws, ns, s);
     else hss_step_generic<T>(h, L, ws, ns, s);
 }

@@ -228,7 +228,7 @@ using IC = std::integral_constant<int, U>;
 // 2C + 1 takes (ce(C) + ce(C + 1)) / 8 (exact powers of two).  The coarse
 // plane for fine step p is written to LDS one step ahead and requested two
 // steps ahead of that; the march then starts on an even plane.
-template <typename T, typename TI, int FIRST, int NS, bool PRO, int UPD, int TH>
+template <typename T, typename TI, int FIRST, int NS, bool PRO, int UPD, int TH, bool DIR>
 __global__ __launch_bounds__(Tile<TH>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T s, Vec<const cx<TI>> X,
                                               Vec<const cx<T>> Bv, Vec<const cx<T>> Ec,
                                               Vec<cx<T>> Rho, Vec<cx<T>> Y, Grid3F g) {
@@ -254,6 +254,12 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T 
     const bool bx = (i == 0) | (i == n), by = (j == 0) | (j == n);
     const bool edge_wave = __any((int)(inmesh & (bx | by)));
     const int cxy = (int)bx + (int)by;  // boundary coordinates in x and y
+    // DIR: outputs on the nodes of Dirichlet faces are zero (the column lies
+    // on an x or y Dirichlet face, or the plane is a z Dirichlet face)
+    const unsigned dm = DIR ? L.dir : 0u;
+    const bool dcol = DIR && (((dm & 1u) && i == 0) || ((dm & 2u) && i == n) ||
+                              ((dm & 4u) && j == 0) || ((dm & 8u) && j == n));
+    auto dfix = [&](int l) { return dcol || ((dm & 16u) && l == 0) || ((dm & 32u) && l == n); };
     // the Jacobi factor w/D of this column on plane l, indexed by the number
     // of boundary coordinates (the same on every lane of an interior wave)
     auto odf = [&](int l) {
@@ -377,12 +383,14 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T 
         if (PW) {
             if (q1ok) {
                 if (FIRST == F_HSS0) {
-                    const cx<T> r = s * bcur;
+                    cx<T> r = s * bcur;
+                    if (DIR) r = csel(dfix(q1), z, r);
                     if (owned && q1 >= z0 && q1 < z1) sto(rs + (long long)q1 * sz, ob, r);
                     x1 = od1 * r;
                     bq = r;
                 } else {
                     x1 = od1 * bcur;
+                    if (DIR) x1 = csel(dfix(q1), z, x1);
                     bq = bcur;
                 }
             }
@@ -399,13 +407,17 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T 
             if (q1ok && st1) {
                 if (FIRST == F_APPLY) {
                     x1 = ax;
+                    if (DIR) x1 = csel(dfix(q1), z, x1);
                 } else if (FIRST == F_RESID) {
                     x1 = s * (bcur - ax);
+                    if (DIR) x1 = csel(dfix(q1), z, x1);
                 } else if (FIRST == F_JAC || J0) {
                     x1 = cfma(od1, bcur - ax, xc);
+                    if (DIR) x1 = csel(dfix(q1), z, x1);
                     bq = bcur;
                 } else {  // F_HSS
-                    const cx<T> r = s * (bcur - ax);
+                    cx<T> r = s * (bcur - ax);
+                    if (DIR) r = csel(dfix(q1), z, r);
                     if (owned && q1 >= z0 && q1 < z1) sto(rs + (long long)q1 * sz, ob, r);
                     x1 = od1 * r;
                     bq = r;
@@ -443,7 +455,8 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T 
                 plane_terms<T>(L, edge_wave, a0, H, V, a2, bx, by, (qm == 0) | (qm == n), u1, u0);
             if (owned && q2 >= z0 && q2 < z1) {
                 const cx<T> od2 = odf(q2);
-                const cx<T> x2 = cfma(od2, b2 - (acc2 + u1), xc2);
+                cx<T> x2 = cfma(od2, b2 - (acc2 + u1), xc2);
+                if (DIR) x2 = csel(dfix(q2), z, x2);
                 sto(ys + (long long)q2 * sz, ob, UPD == 1 ? yo + x2 : x2);
             }
             acc2 = U1p + u0;
@@ -477,7 +490,7 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_pass(Op3F<T> L, Op3F<T> B, T 
 // planes (weight 1 on plane 2 L, 1/2 on 2 L +- 1).  Segments own coarse
 // planes [Z0, Z0 + tz).  The march starts on an even plane and is unrolled
 // as in k3_pass.
-template <typename T, int TH>
+template <typename T, int TH, bool DIR>
 __global__ __launch_bounds__(Tile<TH>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>> X, Vec<const cx<T>> Bv,
                                                      Vec<cx<T>> Bc, Grid3F g) {
     constexpr int LH = Tile<TH>::H, RCH = Tile<TH>::RCH;
@@ -510,6 +523,13 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>
     const int ci = (int)threadIdx.x % RC, cj = (int)threadIdx.x / RC;
     const int I = RC * tx + ci, J = RCH * ty + cj;
     const bool cown = cst & (I <= nc) & (J <= nc);
+    // DIR: the residual is cleared on the fine nodes of Dirichlet faces and
+    // the restricted value on the coarse ones
+    const unsigned dm = DIR ? L.dir : 0u;
+    const bool dcol = DIR && (((dm & 1u) && i == 0) || ((dm & 2u) && i == n) ||
+                              ((dm & 4u) && j == 0) || ((dm & 8u) && j == n));
+    const bool ccol = DIR && (((dm & 1u) && I == 0) || ((dm & 2u) && I == nc) ||
+                              ((dm & 4u) && J == 0) || ((dm & 8u) && J == nc));
     const unsigned occ = cown ? (unsigned)(J * syc + I) * (unsigned)sizeof(cx<T>) : 0u;
 
     // unconditional loads (see k3_pass), masked where consumed
@@ -552,6 +572,7 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>
         }
         cx<T> r = z;
         if (st1 && inmesh && q >= 0 && q <= n) r = bcur - (acc + t1);
+        if (DIR) r = csel(dcol || ((dm & 16u) && q == 0) || ((dm & 32u) && q == n), z, r);
         acc = T1p + t0;
         T1p = t1;
         pres[kb][ly][lx & 1][lx >> 1] = r;
@@ -571,7 +592,9 @@ __global__ __launch_bounds__(Tile<TH>::FT) void k3_rr(Op3F<T> L, Vec<const cx<T>
             const int q2 = q - 1;  // same parity as p
             if (kb == 1) {  // q2 odd
                 const int Lc = (q2 - 1) >> 1;  // coarse plane completed by this odd plane
-                if (cown && Lc >= Z0 && Lc < Z1) sto(bc + (long long)Lc * szc, occ, cur + (T)0.5 * r2);
+                cx<T> v = cur + (T)0.5 * r2;
+                if (DIR) v = csel(ccol || ((dm & 16u) && Lc == 0) || ((dm & 32u) && Lc == nc), z, v);
+                if (cown && Lc >= Z0 && Lc < Z1) sto(bc + (long long)Lc * szc, occ, v);
                 half = (T)0.5 * r2;
             } else {
                 cur = half + r2;
@@ -663,7 +686,7 @@ int seg_planes_rr(int cplanes, int tiles, int nslots, int resident) {
     return best;
 }
 
-template <typename T, typename TI, int F, int NS, bool PRO, int UPD, int TH>
+template <typename T, typename TI, int F, int NS, bool PRO, int UPD, int TH, bool DIR>
 void launch_pass_h(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
                    Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
                    int tz) {
@@ -673,10 +696,18 @@ void launch_pass_h(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<
     g.tiles_y = (n + 1 + ownh - 1) / ownh;
     g.tz = tz > 0 ? tz
                   : seg_planes(n + 1, g.tiles_x * g.tiles_y, nslots,
-                               resident_units<k3_pass<T, TI, F, NS, PRO, UPD, TH>, Tile<TH>::FT>());
+                               resident_units<k3_pass<T, TI, F, NS, PRO, UPD, TH, DIR>, Tile<TH>::FT>());
     g.segs = (n + 1 + g.tz - 1) / g.tz;
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
-    k3_pass<T, TI, F, NS, PRO, UPD, TH><<<grid, Tile<TH>::FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g);
+    k3_pass<T, TI, F, NS, PRO, UPD, TH, DIR><<<grid, Tile<TH>::FT, 0, st>>>(L, B, s, X, Bv, Ec, Rho, Y, g);
+}
+
+template <typename T, typename TI, int F, int NS, bool PRO, int UPD, int TH>
+void launch_pass_d(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<const cx<TI>> X,
+                   Vec<const cx<T>> Bv, Vec<const cx<T>> Ec, Vec<cx<T>> Rho, Vec<cx<T>> Y, int nslots,
+                   int tz) {
+    if (L.dir) launch_pass_h<T, TI, F, NS, PRO, UPD, TH, true>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
+    else launch_pass_h<T, TI, F, NS, PRO, UPD, TH, false>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
 }
 
 template <typename T, typename TI, int F, int NS, bool PRO, int UPD>
@@ -685,14 +716,14 @@ void launch_pass(hipStream_t st, const Op3F<T>& L, const Op3F<T>& B, T s, Vec<co
                  int tz) {
     if constexpr (short_rows<T>() != tall_rows<T>()) {
         if (L.n < HELM_K3_TALL_N) {
-            launch_pass_h<T, TI, F, NS, PRO, UPD, short_rows<T>()>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
+            launch_pass_d<T, TI, F, NS, PRO, UPD, short_rows<T>()>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
             return;
         }
     }
-    launch_pass_h<T, TI, F, NS, PRO, UPD, tall_rows<T>()>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
+    launch_pass_d<T, TI, F, NS, PRO, UPD, tall_rows<T>()>(st, L, B, s, X, Bv, Ec, Rho, Y, nslots, tz);
 }
 
-template <typename T, int TH>
+template <typename T, int TH, bool DIR>
 void rr3d_h(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<cx<T>> Bc,
             int nslots, int tz) {
     const int nc = L.n / 2;
@@ -701,10 +732,17 @@ void rr3d_h(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T
     g.tiles_y = (nc + 1 + Tile<TH>::RCH - 1) / Tile<TH>::RCH;
     g.tz = tz > 0 ? tz
                   : seg_planes_rr(nc + 1, g.tiles_x * g.tiles_y, nslots,
-                                  resident_units<k3_rr<T, TH>, Tile<TH>::FT>());
+                                  resident_units<k3_rr<T, TH, DIR>, Tile<TH>::FT>());
     g.segs = (nc + 1 + g.tz - 1) / g.tz;
     const dim3 grid((unsigned)(g.tiles_x * g.tiles_y * g.segs * nslots));
-    k3_rr<T, TH><<<grid, Tile<TH>::FT, 0, st>>>(L, X, Bv, Bc, g);
+    k3_rr<T, TH, DIR><<<grid, Tile<TH>::FT, 0, st>>>(L, X, Bv, Bc, g);
+}
+
+template <typename T, int TH>
+void rr3d_d(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>> Bv, Vec<cx<T>> Bc,
+            int nslots, int tz) {
+    if (L.dir) rr3d_h<T, TH, true>(st, L, X, Bv, Bc, nslots, tz);
+    else rr3d_h<T, TH, false>(st, L, X, Bv, Bc, nslots, tz);
 }
 
 }  // namespace
@@ -750,11 +788,11 @@ void rr3d(hipStream_t st, const Op3F<T>& L, Vec<const cx<T>> X, Vec<const cx<T>>
           int nslots, int tz) {
     if constexpr (short_rows<T>() != tall_rows<T>()) {
         if (L.n < HELM_K3_TALL_N) {
-            rr3d_h<T, short_rows<T>()>(st, L, X, Bv, Bc, nslots, tz);
+            rr3d_d<T, short_rows<T>()>(st, L, X, Bv, Bc, nslots, tz);
             return;
         }
     }
-    rr3d_h<T, tall_rows<T>()>(st, L, X, Bv, Bc, nslots, tz);
+    rr3d_d<T, tall_rows<T>()>(st, L, X, Bv, Bc, nslots, tz);
 }
 
 template bool pass3d<double, double>(hipStream_t, const Op3F<double>&, const Op3F<double>&, int, int,

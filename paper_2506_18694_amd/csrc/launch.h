@@ -128,6 +128,7 @@ struct Op3F {
     cx<T> e1[3], e0[3], f0[3];  // their changes on a boundary column (see kernels3d_fused.hip)
     cx<T> od[4];
     int n;
+    unsigned dir;  // Dirichlet faces (x0=1 .. z1=32): every pass writes zero on their nodes
 };
 struct Grid3F {
     int tiles_x, tiles_y, segs, tz;  // tiles per side, plane segments, planes per segment
