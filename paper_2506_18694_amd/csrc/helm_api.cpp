@@ -94,11 +94,12 @@ template <typename T>
 cx<T> tocx(zd z) { return mk((T)z.real(), (T)z.imag()); }
 
 template <typename T>
-Op2<T> make_op2(const Coef& cf, int n, double omega) {
+Op2<T> make_op2(const Coef& cf, int n, double omega, unsigned dir = 0) {
     const double h = 1.0 / n;
     const zd A = cf.a, Bm = cf.b * (h * h / 24.0), Cg = cf.c * (h / 6.0);
     const zd wC = 4.0 * A + 12.0 * Bm, wAx = -A + 2.0 * Bm, wDg = 2.0 * Bm;
     Op2<T> o;
+    o.dir = dir;
     o.A = tocx<T>(A);
     o.Bm = tocx<T>(Bm);
     o.Cg = tocx<T>(Cg);
@@ -309,10 +310,10 @@ struct helm_s {
     // not unknowns: every vector the library produces is zero there, and
     // the operators' rows on the other nodes are those of the Sommerfeld
     // operator (whose couplings to the face nodes meet zeros).  The 3D
-    // z-marching passes clear the face nodes of every stage output
-    // themselves; 2D handles run the one-pass-per-launch path with the faces
-    // cleared after every pass (the fused 2D passes would carry nonzero face
-    // values between their internal sweeps).
+    // z-marching passes and the 2D streaming kernels clear the face nodes
+    // of every stage output themselves; the other paths (2D levels below
+    // the streaming ones, fused kernels switched off) run one pass per
+    // launch with the faces cleared after every pass.
     unsigned dir = 0;
 
     Coef coef(int op) const {
@@ -598,7 +599,14 @@ void run_small(helm_t* h, int l0, Vec<const cx<T>> b, Vec<cx<T>> x, int ns) {
 // Levels that run with the register-streaming kernels: every 2D level
 // above the small-level kernel, unless switched off.
 inline bool use_stream(const helm_t* h, int l) {
-    return h->dim == 2 && !h->opts.no_stream && h->nl[l] >= 16 && h->dir == 0;
+    return h->dim == 2 && !h->opts.no_stream && h->nl[l] >= 16;
+}
+
+// 2D handles that run the fused HSS step (with Dirichlet faces only where
+// the finest level streams: the streaming kernels clear the faces
+// themselves, the LDS-tiled ones do not)
+inline bool fused2d(const helm_t* h) {
+    return h->dim == 2 && (!h->dir || (use_stream(h, 0) && h->levels > 1));
 }
 
 // Fused 2D cycle from a zero initial guess on level l (l >= 1 inside the HSS
@@ -618,7 +626,12 @@ Vec<cx<T>> vcycle2d_zero(helm_t* h, const Layout& Lw, void* ws, int l, Vec<const
         run_small<T>(h, l, b, x, ns);
         return x;
     }
-    const Op2<T> L = make_op2<T>(h->coef(HELM_OP_L), h->nl[l], h->omega);
+    if (h->dir && !use_stream(h, l)) {
+        // Dirichlet faces below the streaming levels: one pass per launch
+        vcycle<T>(h, Lw, ws, l, b, x, t, ns);
+        return x;
+    }
+    const Op2<T> L = make_op2<T>(h->coef(HELM_OP_L), h->nl[l], h->omega, h->dir);
     const long long Nc = h->Nl[l + 1];
     Vec<cx<T>> bc = at_ws<cx<T>>(ws, Lw.mg_b[l + 1], Nc);
     Vec<cx<T>> xc = at_ws<cx<T>>(ws, Lw.mg_x[l + 1], Nc);
@@ -650,8 +663,8 @@ void hss_step2d(helm_t* h, const Layout& Lw, void* ws, int ns, int s) {
     Vec<cx<T>> xa = at_ws<cx<T>>(ws, Lw.mg_x[0], N);
     Vec<cx<T>> xb = at_ws<cx<T>>(ws, Lw.mg_t[0], N);
     const T c = (T)(2.0 * h->k / (h->k + 1.0));
-    const Op2<T> L = make_op2<T>(h->coef(HELM_OP_L), h->nl[0], h->omega);
-    const Op2<T> Bs = make_op2<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega);
+    const Op2<T> L = make_op2<T>(h->coef(HELM_OP_L), h->nl[0], h->omega, h->dir);
+    const Op2<T> Bs = make_op2<T>(h->coef(HELM_OP_BSHIFT), h->nl[0], h->omega, h->dir);
     Vec<const cx<T>> uin = s == 0 ? Vec<const cx<T>>{} : cst(u);
     if (h->levels == 1) {
         // single level: every cycle is the exact coarse solve
@@ -888,7 +901,7 @@ void hss_step(helm_t* h, const Layout& L, void* ws, int ns, int s) {
             return;
         }
     }
-    if (h->dim == 2 && !h->dir) hss_step2d<T>(h, L, ws, ns, s);
+    if (fused2d(h)) hss_step2d<T>(h, L, ws, ns, s);
     else if (fused3d(h) && h->levels > 1) hss_step3d_fused<T>(h, L, ws, ns, s);
     else hss_step_generic<T>(h, L, ws, ns, s);
 }
@@ -1128,7 +1141,7 @@ void vcycle_entry(helm_t* h, const Layout& Lw, void* ws, const void* b, void* x,
             return;
         }
     }
-    if ((h->dim == 2 && !h->dir) || fused3d(h)) {
+    if (fused2d(h) || fused3d(h)) {
         Vec<cx<T>> r = h->dim == 2 ? vcycle2d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns)
                                    : vcycle3d_zero<T>(h, Lw, ws, 0, bv, xv, tv, ns);
         if (r.base != xv.base) copy_cast<T, T>(h->stream, N, cst(r), xv, ns);

@@ -94,6 +94,7 @@ struct Op2 {
     cx<T> dC, dN, kA, kB;
     T omega;
     int n;
+    unsigned dir;  // Dirichlet faces (x0=1, x1=2, y0=4, y1=8) for the streaming kernels
 };
 
 template <typename T>

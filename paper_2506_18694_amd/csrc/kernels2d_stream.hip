@@ -280,6 +280,20 @@ __device__ __forceinline__ cx<T> clip(cx<T> v, const Lanes<T>& ln, int r, int n)
     return v;
 }
 
+// Dirichlet faces (DIR): zero on the nodes of the faces set in L.dir, for
+// this lane's column and row r (uniform across the wave)
+template <bool DIR, typename T>
+__device__ __forceinline__ cx<T> dclip(cx<T> v, const Op2<T>& L, const Lanes<T>& ln, int r) {
+    if constexpr (!DIR) {
+        return v;
+    } else {
+        const unsigned d = L.dir;
+        const bool f = ((d & 1u) && ln.i == 0) || ((d & 2u) && ln.i == L.n) || ((d & 4u) && r == 0) ||
+                       ((d & 8u) && r == L.n);
+        return sel(f, zero_cx<T>(), v);
+    }
+}
+
 struct Unit {
     int slot, strip, seg;
 };
@@ -349,7 +363,7 @@ struct SweepIn {
     cx<T> x, b, e0, e1, u;
 };
 
-template <typename T, int S, bool PROLONG, bool RESID, bool UPDATE>
+template <typename T, int S, bool PROLONG, bool RESID, bool UPDATE, bool DIR>
 __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) void k_stream_sweeps(
     Op2<T> L, Vec<const cx<T>> Xin, Vec<const cx<T>> Ec, Vec<const cx<T>> Bv, Vec<cx<T>> Xout,
     Vec<cx<T>> Bc, StreamGrid gr) {
@@ -407,16 +421,17 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         using Q = Slots<P>;
         cx<T> x0 = in.x;
         if (PROLONG) x0 = axpy_real((T)0.5, in.e0 + in.e1, x0);
-        ring_push<P>(rg[0], clip<MODE>(x0, ln, t, n));
+        ring_push<P>(rg[0], dclip<DIR>(clip<MODE>(x0, ln, t, n), L, ln, t));
         bq[P % NB] = in.b;
 #pragma unroll
         for (int s = 1; s <= S; ++s) {
             const int r = t - s;
             const Ring<T>& g = rg[s - 1];
             const cx<T> br = bq[qslot<NB>(P, s)];
-            const cx<T> v = clip<MODE>(
-                cfma(ring_jf<MODE>(ln, r, n), br - ring_apply<P, MODE>(L, g, ln, r), g.v[Q::C]), ln,
-                r, n);
+            const cx<T> v = dclip<DIR>(
+                clip<MODE>(cfma(ring_jf<MODE>(ln, r, n), br - ring_apply<P, MODE>(L, g, ln, r), g.v[Q::C]),
+                           ln, r, n),
+                L, ln, r);
             if (s < S) {
                 ring_push<P>(rg[s], v);
             } else {
@@ -428,11 +443,12 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
             // residual of the final iterate, row t - S - 1
             const int r = t - S - 1;
             const cx<T> rv = bq[qslot<NB>(P, S + 1)] - ring_apply<P, MODE>(L, rg[S], ln, r);
-            ring_push<P>(rg[S + 1], clip<MODE>(rv, ln, r, n));
-            // restriction at the fine row t - S - 2 when it is even
+            ring_push<P>(rg[S + 1], dclip<DIR>(clip<MODE>(rv, ln, r, n), L, ln, r));
+            // restriction at the fine row t - S - 2 when it is even (a coarse
+            // node on a Dirichlet face sits on a fine one)
             const int rr = t - S - 2;
             if (!(rr & 1) & (rr >= y0) & (rr < y1)) {
-                const cx<T> v = ring_restrict<P>(rg[S + 1]);
+                const cx<T> v = dclip<DIR>(ring_restrict<P>(rg[S + 1]), L, ln, rr);
                 if (own_even) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
             }
         }
@@ -487,7 +503,7 @@ struct PreIn {
     cx<T> s, u;  // b or R, and u
 };
 
-template <typename T, int HSS>
+template <typename T, int HSS, bool DIR>
 __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) void k_stream_pre(
     Op2<T> L, Op2<T> Bs, T c, Vec<const cx<T>> U, Vec<const cx<T>> Rv, Vec<cx<T>> Rho,
     Vec<const cx<T>> Bv, Vec<cx<T>> X, Vec<cx<T>> Bc, StreamGrid gr) {
@@ -547,6 +563,7 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
             rb = t;
             bnew = in.s;
         }
+        bnew = dclip<DIR>(bnew, L, ln, rb);
         if (HSS != 0 && (own & (rb >= y0) & (rb < y1))) rho[(long long)rb * np + ln.i] = bnew;
         bq[P % 3] = bnew;
         // first sweep (pointwise): row rb
@@ -554,22 +571,24 @@ __global__ __launch_bounds__(WAVE * SW) __attribute__((amdgpu_waves_per_eu(2))) 
         // second sweep: row rb - 1, written
         {
             const int r = rb - 1;
-            const cx<T> v =
+            const cx<T> v = dclip<DIR>(
                 cfma(ring_jf<MODE>(ln, r, n), bq[qslot<3>(P, 1)] - ring_apply<P, MODE>(L, g1, ln, r),
-                     g1.v[Q::C]);
+                     g1.v[Q::C]),
+                L, ln, r);
             if (own & (r >= y0) & (r < y1)) x[(long long)r * np + ln.i] = v;
             ring_push<P>(g2, clip<MODE>(v, ln, r, n));
         }
         // residual: row rb - 2
         {
             const int r = rb - 2;
-            ring_push<P>(gr3, clip<MODE>(bq[qslot<3>(P, 2)] - ring_apply<P, MODE>(L, g2, ln, r), ln, r, n));
+            ring_push<P>(gr3, dclip<DIR>(clip<MODE>(bq[qslot<3>(P, 2)] - ring_apply<P, MODE>(L, g2, ln, r), ln, r, n),
+                                         L, ln, r));
         }
         // restriction at the fine row rb - 3 when even
         {
             const int rr = rb - 3;
             if (!(rr & 1) & (rr >= y0) & (rr < y1)) {
-                const cx<T> v = ring_restrict<P>(gr3);
+                const cx<T> v = dclip<DIR>(ring_restrict<P>(gr3), L, ln, rr);
                 if (own_even) bc[(long long)(rr >> 1) * npc + (ln.i >> 1)] = v;
             }
         }
@@ -661,7 +680,7 @@ static unsigned stream_blocks(const StreamGrid& g) {
     return g.eblocks + (g.units - g.edge_units + SW - 1) / SW;
 }
 
-enum StreamKind : int { SK_S4R = 0, SK_S2P, SK_S2R, SK_S4P, SK_S1, SK_PRE0, SK_PRE1, SK_PRE2 };
+enum StreamKind : int { SK_S4R = 0, SK_S2P, SK_S2R, SK_S4P, SK_S1, SK_PRE0, SK_PRE1, SK_PRE2, SK_DIR = 16 };
 
 struct RowsKey {
     int kind, n, ns, bytes;
@@ -738,11 +757,15 @@ bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> X
     else if (S == 4 && pro && !resid && !update) kind = SK_S4P;
     else if (S == 1 && !pro && !resid && !update) kind = SK_S1;
     if (kind < 0) return false;
+    const bool dir = L.dir != 0u;
     auto launch = [&](int H) {
         const StreamGrid g = stream_grid(L.n, halo, ns, H);
         const unsigned nb = stream_blocks(g);
-#define HELM_STREAM(SS, PP, RR, UU) \
-    k_stream_sweeps<T, SS, PP, RR, UU><<<nb, WAVE * SW, 0, st>>>(L, Xin, Ec, B, Xout, Bc, g)
+#define HELM_STREAM(SS, PP, RR, UU)                                                                      \
+    do {                                                                                                 \
+        if (dir) k_stream_sweeps<T, SS, PP, RR, UU, true><<<nb, WAVE * SW, 0, st>>>(L, Xin, Ec, B, Xout, Bc, g); \
+        else k_stream_sweeps<T, SS, PP, RR, UU, false><<<nb, WAVE * SW, 0, st>>>(L, Xin, Ec, B, Xout, Bc, g); \
+    } while (0)
         if (kind == SK_S4R) HELM_STREAM(4, true, true, false);
         else if (kind == SK_S2P && update) HELM_STREAM(2, true, false, true);
         else if (kind == SK_S2P) HELM_STREAM(2, true, false, false);
@@ -752,7 +775,7 @@ bool stream_sweeps_2d(hipStream_t st, const Op2<T>& L, int S, Vec<const cx<T>> X
 #undef HELM_STREAM
     };
     // u += x is not safe to repeat: the update launch only looks up
-    launch(stream_rows(st, RowsKey{kind, L.n, ns, (int)sizeof(T)}, halo, !update, launch));
+    launch(stream_rows(st, RowsKey{kind + (dir ? SK_DIR : 0), L.n, ns, (int)sizeof(T)}, halo, !update, launch));
     return true;
 }
 
@@ -762,17 +785,22 @@ void stream_pre_2d(hipStream_t st, const Op2<T>& L, const Op2<T>& Bs, T c, Vec<c
                    Vec<cx<T>> Bc, int ns) {
     const int hss = B.base ? 0 : (U.base ? 1 : 2);
     const int halo = 3 + (hss == 1 ? 1 : 0);
+    const bool dir = L.dir != 0u;
     auto launch = [&](int H) {
         const StreamGrid g = stream_grid(L.n, halo, ns, H);
         const unsigned nb = stream_blocks(g);
-        if (hss == 0)
-            k_stream_pre<T, 0><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
-        else if (hss == 1)
-            k_stream_pre<T, 1><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
-        else
-            k_stream_pre<T, 2><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g);
+#define HELM_PRE(HH)                                                                          \
+    do {                                                                                      \
+        if (dir) k_stream_pre<T, HH, true><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g); \
+        else k_stream_pre<T, HH, false><<<nb, WAVE * SW, 0, st>>>(L, Bs, c, U, R, Rho, B, X, Bc, g); \
+    } while (0)
+        if (hss == 0) HELM_PRE(0);
+        else if (hss == 1) HELM_PRE(1);
+        else HELM_PRE(2);
+#undef HELM_PRE
     };
-    launch(stream_rows(st, RowsKey{SK_PRE0 + hss, L.n, ns, (int)sizeof(T)}, halo, true, launch));
+    launch(stream_rows(st, RowsKey{SK_PRE0 + hss + (dir ? SK_DIR : 0), L.n, ns, (int)sizeof(T)}, halo, true,
+                       launch));
 }
 
 template bool stream_sweeps_2d<double>(hipStream_t, const Op2<double>&, int, Vec<const cxd>,

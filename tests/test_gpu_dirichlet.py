@@ -245,15 +245,18 @@ def test_3d_128_matches_masked_impedance_rows(prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 5e-4)])
-def test_3d_fused_and_one_pass_paths_agree(prec, tol):
-    """3D handles with Dirichlet faces run the z-marching passes with the
-    faces cleared inside every stage; with the fused passes switched off
-    they run one pass per launch and a mask after each.  Both compute the
-    oracle's preconditioner, and the cycle of each matches the oracle's."""
-    dim, n, levels, k, cycles, bits = 3, 24, 3, 4.0, 2, 0b101001
+@pytest.mark.parametrize("dim,n,levels,k,bits", [(3, 24, 3, 4.0, 0b101001), (2, 96, 4, 9.0, 0b1001),
+                                                 (2, 64, 3, 7.0, 0b0111)])
+def test_fused_and_one_pass_paths_agree(dim, n, levels, k, bits, prec, tol):
+    """Handles with Dirichlet faces run the fused passes (3D z-marching, 2D
+    register streaming on the levels of at least 16 cells) with the faces
+    cleared inside every stage; with the fused passes switched off they run
+    one pass per launch and a mask after each.  Both compute the oracle's
+    preconditioner, and the cycle of each matches the oracle's."""
+    cycles = 2
     faces = _names(bits)
     pr = osolver.Problem(dim, n, k, k, levels=levels, cycles=cycles, dirichlet=faces)
-    v = W.random_complex((2, (n + 1) ** 3), 23)
+    v = W.random_complex((2, (n + 1) ** dim), 23)
     vm = v.copy()
     vm[:, pr.fixed] = 0.0
     ref = np.stack([pr.precond(vi, inner="mg") for vi in vm])
