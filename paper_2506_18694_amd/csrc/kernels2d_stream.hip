@@ -24,7 +24,9 @@
 // is wider than the mesh, in its lanes past column n.  The interior stencil
 // plus the boundary corrections of the operator record (dC, dN, kA, kB) then
 // gives the element rows of the edge and corner nodes.  Only owned nodes are
-// written.
+// written.  With Dirichlet faces (the DIR instantiations) every stage output,
+// the HSS residual and the restricted values are also cleared on the nodes
+// of those faces, which are not unknowns.
 //
 // The march runs in unrolled blocks of steps: within a block the three-row
 // rings, the queue of right-hand-side rows and the input buffers rotate by
