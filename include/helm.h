@@ -127,8 +127,9 @@ typedef struct {
        them on both levels, and the coarsest-mesh matrix gets identity rows
        and columns there.  Every vector a call writes is zero on Dirichlet
        nodes; vectors passed to the per-step calls must be zero there too
-       (helm_solve and helm_precondition zero their inputs there
-       themselves).  Primal P1/Q1 element with V cycles only. */
+       (helm_solve, helm_precondition and helm_hss_history take their
+       inputs as zero there themselves).  Primal P1/Q1 element with V
+       cycles only. */
     unsigned dirichlet_faces;
 } helm_bc;
 

@@ -1414,8 +1414,16 @@ void hss_history(helm_t* h, const Layout& Lw, void* ws, const cxd* v, Vec<cx<T>>
     const Vec<const cx<T>> u = cst(at_ws<cx<T>>(ws, Lw.u, N));
     const Coef cb = h->coef(HELM_OP_BSHIFT);
     std::vector<double> hn(2 * (size_t)ns);
-    copy_cast<T, double>(s, N, vv, at_ws<cx<T>>(ws, Lw.R, N), ns);
-    norm2(s, N, vv, d_npart, d_norm, 1, ns);
+    if (h->dir && !h->mixed) {
+        // v is taken as zero on the Dirichlet nodes, as the residuals below
+        copy_cast<double, double>(s, N, vv, rv, ns);
+        dir_mask<double>(h, s, 0, rv, ns);
+        copy_cast<T, double>(s, N, cst(rv), at_ws<cx<T>>(ws, Lw.R, N), ns);
+        norm2(s, N, cst(rv), d_npart, d_norm, 1, ns);
+    } else {
+        copy_cast<T, double>(s, N, vv, at_ws<cx<T>>(ws, Lw.R, N), ns);
+        norm2(s, N, vv, d_npart, d_norm, 1, ns);
+    }
     HIPCHK(hipMemcpyAsync(hn.data(), d_norm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int c = 0; c < ns; ++c) res[(size_t)c * (S + 1)] = hn[c];

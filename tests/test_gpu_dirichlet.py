@@ -171,9 +171,11 @@ def test_preconditioner_matches_oracle(dim, n, levels, k, cycles, bits, prec, to
     ref = np.stack([pr.precond(vi, inner="mg") for vi in vm])
     assert rel_l2(z, ref) < tol
     assert np.abs(z[:, pr.fixed]).max() == 0.0
-    # the diagnostic path computes the same preconditioner
+    # the diagnostic path computes the same preconditioner, and its first
+    # entry is the norm of v without its Dirichlet-node values
     zh, res = s.hss_history(to_dev(v))
     assert rel_l2(to_host(zh), z) < (1e-13 if prec == "fp64" else 1e-6)
+    assert np.abs(res[:, 0] / np.linalg.norm(vm, axis=1) - 1).max() < 1e-12
     s.close()
 
 
