@@ -25,10 +25,13 @@ solver     the assembled end-to-end solve used as the parity reference
 
 Parity status: every function above is pinned by a CPU test against a
 closed form, an invariant of the discretisation, a textbook convergence rate,
-an independent library routine, or a value printed in the paper.  Two
-quantities have no such pin ("parity unpinned"): the outer iteration count of
-the V(2,2)-Jacobi preconditioned solve at the benchmark settings and the
-multigrid contraction factor there; the paper prints neither.
+an independent library routine, or a value printed in the paper.  The
+two-grid contraction of the V(2,2)-Jacobi cycle is pinned by local Fourier
+analysis on meshes with every face Dirichlet.  Two quantities have no exact
+pin ("parity unpinned"): the outer iteration count of the V(2,2)-Jacobi
+preconditioned solve at the benchmark settings and the multigrid
+contraction factor there (impedance faces, many levels); the paper prints
+neither.
 """
 
 from . import fem, operators, hss, multigrid, krylov, solver  # noqa: F401
