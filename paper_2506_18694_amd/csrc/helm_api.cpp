@@ -172,10 +172,20 @@ Op3F<T> make_op3f(const Coef& cf, int n, double omega, unsigned dir = 0) {
     for (int q = 0; q < 3; ++q) {
         const zd t1 = uK * pk[q] + uM * pm[q];
         const zd t0 = vK * pk[q] + vM * pm[q];
+        const zd tj = -0.5 * t0 + c * pm[q];
         o.i1[q] = tocx<T>(t1);
         o.i0[q] = tocx<T>(t0);
-        o.j0[q] = tocx<T>(-0.5 * t0 + c * pm[q]);  // end plane: T0 / 2 + c PMM
+        o.j0[q] = tocx<T>(tj);  // end plane: T0 / 2 + c PMM
+        o.r1[q] = (T)t1.real();
+        o.r0[q] = (T)t0.real();
+        o.rj[q] = (T)tj.real();
     }
+    // every operator of the primal form has a real stiffness factor a (1, -1
+    // or 0), so the imaginary parts are those of the PMM terms:
+    // Im(t)[q] = k (h/6)^2 (16, 4, 1)[q]
+    o.k1 = (T)(uM.imag() * h6 * h6);
+    o.k0 = (T)(vM.imag() * h6 * h6);
+    o.kj = (T)((-0.5 * vM.imag() + c.imag()) * h6 * h6);
     // a column on bx + by boundary lines (bx, by in {0, 1}) halves the centre
     // of the 1D factors in those directions and adds E = 1:
     //   PMM += (-8 h6^2 nb + 4 h6^2 bx by) a0 - 2 h6^2 w

@@ -88,6 +88,9 @@ constexpr int short_rows() { return sizeof(T) == 4 ? HELM_K3_LH_FP32 : HELM_K3_L
 #ifndef HELM_K3_PF
 #define HELM_K3_PF 2
 #endif
+#ifndef HELM_K3_SPLIT
+#define HELM_K3_SPLIT 1
+#endif
 constexpr int PF = HELM_K3_PF;  // input planes requested ahead of the one in LDS (>= 1)
 
 // Complex values move as one vector load or store (a struct copy could be
@@ -152,9 +155,24 @@ __device__ __forceinline__ void plane_terms(const Op3F<T>& op, bool edge_wave, c
                                             cx<T> V, cx<T> a2, bool bx, bool by, bool bz, cx<T>& T1,
                                             cx<T>& T0) {
     const cx<T> s1 = H + V;
+#if HELM_K3_SPLIT
+    // real weights on (a0, s1, a2), plus i k times the mass pattern
+    // 16 a0 + 4 s1 + a2 (the imaginary part of every weight is that of its
+    // mass term): 20 operations instead of 24 for T1 and T0
+    const T mx = fmat((T)16, a0.x, fmat((T)4, s1.x, a2.x));
+    const T my = fmat((T)16, a0.y, fmat((T)4, s1.y, a2.y));
+    T1 = mk(fmat(op.r1[0], a0.x, fmat(op.r1[1], s1.x, fmat(op.r1[2], a2.x, -op.k1 * my))),
+            fmat(op.r1[0], a0.y, fmat(op.r1[1], s1.y, fmat(op.r1[2], a2.y, op.k1 * mx))));
+    T0 = mk(fmat(op.r0[0], a0.x, fmat(op.r0[1], s1.x, fmat(op.r0[2], a2.x, -op.k0 * my))),
+            fmat(op.r0[0], a0.y, fmat(op.r0[1], s1.y, fmat(op.r0[2], a2.y, op.k0 * mx))));
+    if (bz)
+        T0 = mk(fmat(op.rj[0], a0.x, fmat(op.rj[1], s1.x, fmat(op.rj[2], a2.x, fmat(-op.kj, my, T0.x)))),
+                fmat(op.rj[0], a0.y, fmat(op.rj[1], s1.y, fmat(op.rj[2], a2.y, fmat(op.kj, mx, T0.y)))));
+#else
     T1 = c3(op.i1, a0, s1, a2);
     T0 = c3(op.i0, a0, s1, a2);
     if (bz) T0 = T0 + c3(op.j0, a0, s1, a2);
+#endif
     if (!edge_wave) return;
     const T nb = (T)((int)bx + (int)by), bxy = (bx && by) ? (T)1 : (T)0;
     const cx<T> w = mk((bx ? V.x : (T)0) + (by ? H.x : (T)0), (bx ? V.y : (T)0) + (by ? H.y : (T)0));

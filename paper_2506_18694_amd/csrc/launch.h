@@ -125,6 +125,10 @@ void prolong3d(hipStream_t st, int n, Vec<const cx<T>> E, Vec<cx<T>> X, int nslo
 template <typename T>
 struct Op3F {
     cx<T> i1[3], i0[3], j0[3];  // T1, T0, and T0 of an end plane minus T0, on interior columns
+    // the same weights split (the K factor a is real): real parts, and the
+    // imaginary parts as k * (16, 4, 1) (the in-plane mass pattern)
+    T r1[3], r0[3], rj[3];
+    T k1, k0, kj;
     cx<T> e1[3], e0[3], f0[3];  // their changes on a boundary column (see kernels3d_fused.hip)
     cx<T> od[4];
     int n;
